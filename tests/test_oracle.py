@@ -1,0 +1,323 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types the oracle's own formula: each checks it against
+brute force, an independent LP solver (scipy's HiGHS), a closed form, an
+invariant or finite differences.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import linprog
+
+import oracle as O
+from paper_2510_15649_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def lp_highs(X, y, lam):
+    """Independent reference: the Section 3.1 LP (split coefficients and
+    residuals) handed to scipy's HiGHS solver."""
+    n, p = X.shape
+    c = np.concatenate([lam * np.ones(2 * p), np.ones(2 * n)])
+    A = np.hstack([X, -X, np.eye(n), -np.eye(n)])
+    res = linprog(c, A_eq=A, b_eq=y, bounds=(0, None), method="highs")
+    assert res.status == 0
+    return res.fun, res.x[:p] - res.x[p:2 * p]
+
+
+def f_np(X, y, lam, b):
+    return float(np.abs(y - X @ b).sum() + lam * np.abs(b).sum())
+
+
+# --------------------------------------------------------------------------
+# weighted median (exact 1-D section minimum)
+# --------------------------------------------------------------------------
+
+def test_weighted_median_is_lowest_minimiser():
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        m = int(rng.integers(1, 40))
+        t = np.round(rng.standard_normal(m), int(rng.integers(0, 3)))  # rounding makes ties
+        w = rng.uniform(0.01, 2.0, m)
+        k = O.weighted_median(t, w)
+        g = np.array([np.sum(w * np.abs(v - t)) for v in t])
+        gmin = g.min()
+        assert g[k] <= gmin + 1e-12 * (1 + gmin)
+        # lowest minimiser: every strictly smaller key is strictly worse
+        assert not np.any((t < t[k]) & (g <= gmin + 1e-12 * (1 + gmin)))
+
+
+def test_weighted_median_unit_weights_is_median():
+    rng = np.random.default_rng(2)
+    for m in [1, 2, 3, 7, 10, 31, 64]:
+        t = rng.standard_normal(m)
+        k = O.weighted_median(t, np.ones(m))
+        s = np.sort(t)
+        if m % 2 == 1:
+            assert t[k] == np.median(t)
+        else:  # lower median
+            assert t[k] == s[m // 2 - 1]
+
+
+# --------------------------------------------------------------------------
+# coordinate update = exact minimum along the axis
+# --------------------------------------------------------------------------
+
+def test_coord_update_minimises_section():
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        n, p = int(rng.integers(3, 30)), int(rng.integers(1, 6))
+        X = rng.standard_normal((n, p))
+        y = rng.standard_normal(n) * 2
+        lam = float(10 ** rng.uniform(-2, 1))
+        b = rng.standard_normal(p)
+        j = int(rng.integers(0, p))
+        bn = O.coord_update(X, y, lam, b, j)
+        assert np.all(np.delete(bn, j) == np.delete(b, j))
+        # candidates: every kink of the section, found by the test itself
+        r = y - X @ b + X[:, j] * b[j]
+        cand = np.concatenate([r[X[:, j] != 0] / X[X[:, j] != 0, j], [0.0]])
+        vals = []
+        for v in cand:
+            bb = b.copy()
+            bb[j] = v
+            vals.append(f_np(X, y, lam, bb))
+        assert f_np(X, y, lam, bn) <= min(vals) + 1e-10 * (1 + min(vals))
+
+
+# --------------------------------------------------------------------------
+# exact solvers against an independent LP solver
+# --------------------------------------------------------------------------
+
+def test_brute_force_matches_highs_tiny():
+    rng = np.random.default_rng(4)
+    for _ in range(200):
+        n, p = int(rng.integers(2, 13)), int(rng.integers(1, 5))
+        X = rng.standard_normal((n, p))
+        y = rng.standard_normal(n) * 3
+        lam = float(10 ** rng.uniform(-2, 1.5))
+        fb, bb, _ = O.brute_force(X, y, lam)
+        fh, _ = lp_highs(X, y, lam)
+        assert abs(fb - fh) <= 1e-9 * max(1.0, fh)
+        assert abs(f_np(X, y, lam, bb) - fb) <= 1e-9 * max(1.0, fb)
+
+
+def test_c0_golden_bruteforce():
+    """Stored brute-force optima of the c0 instance (written by
+    tests/golden/make_golden.py from the oracle) still hold, the generator
+    still draws the same instance, and the LP solver agrees."""
+    g = json.load(open(os.path.join(GOLD, "c0_bruteforce.json")))
+    w = W.config0()
+    np.testing.assert_array_equal(w.X64, np.array(g["X64"]))
+    np.testing.assert_array_equal(w.y64, np.array(g["y64"]))
+    for case in g["cases"]:
+        X, y = w.X64, w.y64
+        if case["data"] == "f32":
+            X = X.astype(np.float32).astype(np.float64)
+            y = y.astype(np.float32).astype(np.float64)
+        lam = case["lambda"]
+        fb, bb, nv = O.brute_force(X, y, lam)
+        assert nv == case["vertices"] == 1771  # C(23,3): all non-singular
+        assert abs(fb - case["f"]) <= 1e-12 * case["f"]
+        fh, _ = lp_highs(X, y, lam)
+        assert abs(fh - fb) <= 1e-9 * fb
+        b, info = O.solve(X, y, lam)
+        assert info["certified"]
+        assert abs(info["f"] - fb) <= 1e-10 * fb
+        np.testing.assert_allclose(b, case["b"], rtol=1e-9, atol=1e-12)
+
+
+def test_simplex_and_solve_match_highs():
+    rng = np.random.default_rng(5)
+    for it in range(12):
+        n, p = [(40, 3), (120, 8), (200, 8), (80, 12)][it % 4]
+        X = rng.standard_normal((n, p))
+        bt = np.zeros(p)
+        bt[:3] = rng.uniform(-3, 3, 3)
+        y = X @ bt + rng.laplace(0, 1, n)
+        lam = float(10 ** rng.uniform(-2, 1.5))
+        fh, bh = lp_highs(X, y, lam)
+        fs, bs, u, _ = O.lp_simplex(X, y, lam)
+        assert abs(fs - fh) <= 1e-9 * max(1, fh)
+        # the simplex's duals are a certificate (LP duality, Section 3.1 LP)
+        assert np.max(np.abs(u)) <= 1 + 1e-9
+        assert np.max(np.abs(X.T @ u)) <= lam + 1e-8 * (1 + lam)
+        assert abs(y @ u - fh) <= 1e-8 * max(1, fh)
+        b, info = O.solve(X, y, lam, max_rounds=1)
+        assert info["certified"]
+        assert abs(f_np(X, y, lam, b) - fh) <= 1e-9 * max(1, fh)
+        assert abs(info["gap"]) <= 1e-8 * max(1, fh)
+
+
+def test_solve_random_tiny_all_schedules():
+    """The full method, with and without ternary rounds, reaches brute force's
+    optimum on random tiny problems (n < p included)."""
+    rng = np.random.default_rng(6)
+    for it in range(300):
+        n, p = int(rng.integers(2, 12)), int(rng.integers(1, 5))
+        X = rng.standard_normal((n, p))
+        y = rng.standard_normal(n) * 3
+        lam = float(10 ** rng.uniform(-2, 1.5))
+        fb, _, _ = O.brute_force(X, y, lam)
+        for rounds in (-1, 0, 1):
+            b, info = O.solve(X, y, lam, max_rounds=rounds)
+            assert info["certified"], (it, rounds)
+            assert abs(f_np(X, y, lam, b) - fb) <= 1e-9 * max(1, fb), (it, rounds)
+
+
+# --------------------------------------------------------------------------
+# closed forms
+# --------------------------------------------------------------------------
+
+def test_null_solution_at_lambda_max():
+    """b* = 0 iff ||X^T sign(y)||_inf <= lambda (subgradient condition at 0
+    with no zero y_i)."""
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        n, p = 60, 5
+        X = rng.standard_normal((n, p))
+        y = X[:, 0] * 2 + rng.standard_normal(n)
+        c = X.T @ np.sign(y)
+        lmax = np.max(np.abs(c))
+        b, info = O.solve(X, y, lmax * 1.001)
+        assert np.all(b == 0) and info["certified"]
+        b, info = O.solve(X, y, lmax * 0.999)
+        nz = np.flatnonzero(b)
+        assert list(nz) == [int(np.argmax(np.abs(c)))]
+
+
+def test_p1_is_weighted_median_of_ratios():
+    """p = 1: minimising sum |x_i||b - y_i/x_i| + lambda |b| over b; checked
+    by evaluating f at every candidate kink."""
+    rng = np.random.default_rng(8)
+    for _ in range(50):
+        n = int(rng.integers(1, 40))
+        x = rng.standard_normal(n)
+        y = rng.standard_normal(n) * 2
+        lam = float(10 ** rng.uniform(-2, 1))
+        b, info = O.solve(x[:, None], y, lam)
+        cand = np.concatenate([y / x, [0.0]])
+        vals = [np.sum(np.abs(y - x * v)) + lam * abs(v) for v in cand]
+        assert f_np(x[:, None], y, lam, b) <= min(vals) + 1e-12 * (1 + min(vals))
+        assert info["stage"] == O.STAGE_CCD
+
+
+def test_p2_ternary_chop_exact_without_finisher():
+    """p = 2: the restricted sub-search is a single exact 1-D minimisation,
+    so F(s) is convex and the ternary chop alone reaches the optimum."""
+    rng = np.random.default_rng(9)
+    for _ in range(100):
+        n = int(rng.integers(3, 25))
+        X = rng.standard_normal((n, 2))
+        y = rng.standard_normal(n) * 2
+        lam = float(10 ** rng.uniform(-2, 1))
+        fb, _, _ = O.brute_force(X, y, lam)
+        b, info = O.solve(X, y, lam, use_finisher=0, max_rounds=1)
+        assert info["certified"] and info["stage"] in (O.STAGE_CCD, O.STAGE_TERNARY)
+        assert abs(f_np(X, y, lam, b) - fb) <= 1e-9 * max(1, fb)
+
+
+def test_stuck_point_rescued_by_ternary_chop():
+    """Plain CCD stops at an axis-wise minimum above the optimum (Section
+    3.4); the ternary chop along the locus (Sections 3.5-3.6) reaches it."""
+    g = json.load(open(os.path.join(GOLD, "stuck2d.json")))
+    X, y, lam = np.array(g["X"]), np.array(g["y"]), g["lambda"]
+    fb, bb, _ = O.brute_force(X, y, lam)
+    assert abs(fb - g["f_opt"]) <= 1e-12
+    bc, fc, _ = O.ccd(X, y, lam)
+    assert fc > fb + 0.5  # CCD is stuck
+    ok, _, _, _ = O.certify(X, y, lam, bc)
+    assert not ok  # and the snap alone does not rescue it
+    b, info = O.solve(X, y, lam, use_finisher=0, max_rounds=1)
+    assert info["stage"] == O.STAGE_TERNARY
+    np.testing.assert_allclose(b, bb, rtol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# invariants
+# --------------------------------------------------------------------------
+
+def test_metamorphic_invariants():
+    rng = np.random.default_rng(10)
+    n, p = 50, 4
+    X = rng.standard_normal((n, p))
+    y = X @ np.array([1.0, 0.0, -2.0, 0.5]) + rng.laplace(0, 1, n)
+    lam = 1.5
+    b, info = O.solve(X, y, lam)
+    f = info["f"]
+    perm = rng.permutation(n)
+    b2, i2 = O.solve(X[perm], y[perm], lam)
+    np.testing.assert_allclose(b2, b, rtol=1e-10, atol=1e-12)
+    flip = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    b3, i3 = O.solve(X * flip[:, None], y * flip, lam)
+    np.testing.assert_allclose(b3, b, rtol=1e-10, atol=1e-12)
+    cs = np.array([1.0, -1.0, -1.0, 1.0])
+    b4, i4 = O.solve(X * cs, y, lam)
+    np.testing.assert_allclose(b4, b * cs, rtol=1e-10, atol=1e-12)
+    a = 3.7
+    b5, i5 = O.solve(X, a * y, lam)  # f(a b; a y) = a f(b; y) at fixed lambda
+    np.testing.assert_allclose(b5, a * b, rtol=1e-10, atol=1e-12)
+    assert abs(i5["f"] - a * f) <= 1e-10 * a * f
+    for i in (i2, i3, i4):
+        assert abs(i["f"] - f) <= 1e-10 * f
+
+
+def test_zero_y_and_zero_column():
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((30, 4))
+    b, info = O.solve(X, np.zeros(30), 0.5)
+    assert np.all(b == 0) and info["f"] == 0.0 and info["certified"]
+    X[:, 2] = 0.0
+    y = X @ np.array([1.0, 2.0, 3.0, -1.0]) + rng.laplace(0, 0.1, 30)
+    b, info = O.solve(X, y, 0.5)
+    assert b[2] == 0.0 and info["certified"]
+
+
+# --------------------------------------------------------------------------
+# backward: closed form vs central finite differences of the solution map
+# --------------------------------------------------------------------------
+
+def test_backward_matches_finite_differences():
+    rng = np.random.default_rng(12)
+    checked = 0
+    for it in range(6):
+        n, p = 40, 5
+        X = rng.standard_normal((n, p))
+        y = X @ np.array([1.5, 0, -2, 0, 1]) + rng.laplace(0, 1, n)
+        lam = 2.0
+        b, info = O.solve(X, y, lam)
+        assert info["certified"]
+        if not info["unique"]:
+            continue
+        g = rng.standard_normal(p)
+        dy, dX = O.backward(X, y, lam, b, info["Z"], g)
+        h = 1e-6
+        S = set(np.flatnonzero(b))
+
+        def L(Xp, yp):
+            bb, ii = O.solve(Xp, yp, lam, b_init=b)
+            return g @ bb, set(np.flatnonzero(bb)), ii["Z"]
+
+        entries = [("y", i, None) for i in info["Z"]] + [("X", i, j) for i in info["Z"] for j in S]
+        entries += [("y", int(rng.integers(n)), None), ("X", int(rng.integers(n)), int(rng.integers(p)))]
+        for kind, i, j in entries:
+            Xp, Xm, yp, ym = X.copy(), X.copy(), y.copy(), y.copy()
+            if kind == "y":
+                yp[i] += h
+                ym[i] -= h
+                an = dy[i]
+            else:
+                Xp[i, j] += h
+                Xm[i, j] -= h
+                an = dX[i, j]
+            Lp, Sp, Zp = L(Xp, yp)
+            Lm, Sm, Zm = L(Xm, ym)
+            if not (Sp == Sm == S and Zp == Zm == info["Z"]):
+                continue  # a kink lies within the step
+            fd = (Lp - Lm) / (2 * h)
+            assert abs(fd - an) <= 1e-6 * (1 + abs(an)), (kind, i, j, fd, an)
+            checked += 1
+    assert checked > 50
