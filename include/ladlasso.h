@@ -1,0 +1,208 @@
+/*
+ * ladlasso.h - batched LAD-LASSO solver for AMD MI355X (gfx950).
+ *
+ * Each solve minimises, for one problem (X_k, y_k) and one lambda,
+ *
+ *     f(b) = sum_i |y_i - x_i . b| + lambda * sum_j |b_j|          (Abstract;
+ *                                                   Sections 2.1, 2.2, 3.1)
+ *
+ * by the paper's coordinate descent: exact 1-D minimisation of f along one
+ * axis at a time (Section 3.3; the 1-D section minimum is a weighted median
+ * of the kinks r_i/x_ij + b_j, Section 3.5), then a ternary chop along the
+ * locus of axis-wise minima with the chop axis held fixed in each sub-search
+ * and the range extended until it brackets the minimum (Sections 3.5-3.6).
+ * The end point is snapped to the vertex where p hyperplanes meet (Section
+ * 3.2) and certified by the LP optimality (dual) conditions; when the
+ * certificate fails, primal simplex steps along the edges of the vertex
+ * finish the solve (an addition to the paper, counted in `iters`).
+ *
+ * Conventions
+ *   - All functions are plain C.  `void* stream` is a hipStream_t (NULL =
+ *     the null stream).
+ *   - Arrays named "host" are read synchronously during the call and may be
+ *     freed afterwards.  All other arrays are DEVICE pointers owned by the
+ *     caller; the library never frees or retains them beyond the work it
+ *     enqueues, and reads/writes them only from kernels on `stream`.
+ *   - A return of LADL_OK from an enqueueing call means the work was
+ *     enqueued; per-solve outcomes are reported in `status`.
+ *   - Errors: negative return values; nothing is enqueued when a call
+ *     fails validation.  ladl_error_string() names the code and
+ *     ladl_last_error_detail() holds a message for the last failure of the
+ *     calling thread.
+ *   - Limits: 1 <= p_k <= 32, 1 <= n_k <= 2048.
+ */
+#ifndef LADLASSO_H
+#define LADLASSO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+enum {
+    LADL_OK = 0,
+    LADL_EINVAL = -1,       /* bad argument or layout                        */
+    LADL_EUNSUPPORTED = -2, /* valid but outside the limits above            */
+    LADL_EHIP = -3,         /* a HIP runtime call failed                     */
+    LADL_ENOMEM = -4        /* device or host allocation failed              */
+};
+
+/* per-solve status written to `status` */
+enum {
+    LADL_CERTIFIED = 0,    /* optimality certificate holds with margin: the
+                              minimiser, Z and S are unique                  */
+    LADL_NONUNIQUE = 1,    /* certificate holds at a degenerate or nearly
+                              degenerate vertex: f is optimal, b may not be
+                              the only minimiser                             */
+    LADL_MAXITER = 2,      /* finisher pivot cap reached before certifying   */
+    LADL_NONFINITE = 3,    /* NaN or Inf in this problem's X or y            */
+    LADL_BADLAMBDA = 4,    /* lambda < 0 or NaN                              */
+    LADL_NOTCERTIFIED = 5  /* singular vertex system: best point returned    */
+};
+
+/* option flags */
+enum {
+    LADL_FLAG_GOLDEN = 1,       /* golden-section instead of thirds in the
+                                   ternary chop (same limit, fewer probes)   */
+    LADL_FLAG_NO_FINISHER = 2,  /* stop after the paper's stages             */
+    LADL_FLAG_NO_SNAP = 4       /* no vertex snap/certificate: b is the last
+                                   coordinate-descent point, status MAXITER  */
+};
+
+typedef struct {
+    float tol_f;         /* CCD stops after a sweep that changes nothing or
+                            lowers f by <= tol_f * f          (default 1e-6)  */
+    float tol_s;         /* ternary chop stops at hi - lo <= tol_s *
+                            (1 + |lo| + |hi|)                 (default 2^-20) */
+    float lambda_min;    /* effective lambda = max(lambda, lambda_min); the
+                            paper's tie-breaking minimum (Section 3.6)
+                                                              (default 0)     */
+    int32_t max_sweeps;  /* sweeps per CCD run                (default 64)    */
+    int32_t max_ternary; /* chop iterations per round         (default 48)    */
+    int32_t max_rounds;  /* chop rounds, each on the next axis: 0 none,
+                            -1 one per axis                   (default 1)     */
+    int32_t max_pivots;  /* finisher pivots; <= 0 means 4p + 32 (default 0)   */
+    int32_t flags;       /* LADL_FLAG_*                       (default 0)     */
+    int32_t schedule;    /* -1: autotuned; otherwise a fixed schedule id
+                            (see ladl_schedule_name)          (default -1)    */
+} ladl_options;
+
+/*
+ * Batch layout (HOST arrays).  Problem k has n_k = row_off[k+1] - row_off[k]
+ * rows and p_k features; its X block is row-major n_k x p_k at
+ * X + x_off[k], its y at y + row_off[k].  Solve s runs problem problem[s]
+ * along a lambda path of path_len values lambda[s*path_len + t] (t = 0 ..
+ * path_len-1), each step warm-started from the previous one.
+ * Outputs of (s, t): b at b + path_len*b_off[s] + t*p_s where b_off is the
+ * exclusive prefix sum of p over solves; the scalars at index
+ * s*path_len + t; zero_rows at 32*(s*path_len + t).
+ */
+typedef struct {
+    int32_t num_problems;
+    const int64_t *row_off; /* host [num_problems+1], row_off[0] = 0, non-decreasing */
+    const int64_t *x_off;   /* host [num_problems] or NULL: row_off[k] * p_uniform     */
+    const int32_t *p;       /* host [num_problems] or NULL: p_uniform                  */
+    int32_t p_uniform;
+    int64_t x_len;          /* number of floats in X (bounds check)                    */
+    int64_t y_len;          /* number of floats in y (bounds check)                    */
+    int32_t num_solves;
+    const int32_t *problem; /* host [num_solves] or NULL: solve s uses problem s       */
+    int32_t path_len;       /* >= 1                                                    */
+} ladl_layout;
+
+typedef struct ladl_handle_s *ladl_handle_t;
+typedef struct ladl_plan_s *ladl_plan_t;
+typedef struct ladl_graph_s *ladl_graph_t;
+
+/* Create a handle bound to the calling thread's current HIP device. */
+int ladl_create(ladl_handle_t *handle);
+int ladl_destroy(ladl_handle_t handle);
+
+void ladl_default_options(ladl_options *opt);
+
+/*
+ * Validate a layout and build a plan: per-solve metadata uploaded to the
+ * device, solves bucketed by rows per lane and sorted by decreasing cost
+ * (n_k * p_k) for the persistent work queue, and the schedule chosen.
+ * Synchronous.  The plan keeps its own copies; layout arrays may be freed.
+ */
+int ladl_plan_create(ladl_handle_t handle, const ladl_layout *layout, const ladl_options *opt,
+                     ladl_plan_t *plan);
+int ladl_plan_destroy(ladl_plan_t plan);
+/* total floats of one b output array (all solves, all path steps) */
+int64_t ladl_plan_b_len(ladl_plan_t plan);
+
+/*
+ * Forward solve (the wavefront-per-solve persistent kernels).
+ *   X, y       device, layout as described by the plan
+ *   lambda     device [num_solves * path_len]
+ *   b_init     device, packed like one path step of b (p_s floats per solve
+ *              at b_off[s]), or NULL for zeros: starting point of step 0
+ *   b          device [ladl_plan_b_len]          (output)
+ *   obj        device [num_solves*path_len]      f(b) in fp32 (output)
+ *   active     device [num_solves*path_len]      bit j set iff b_j != 0 (output)
+ *   zero_rows  device [32*num_solves*path_len]   the vertex's zero-residual
+ *              rows (local ids, ascending, -1 padded) (output)
+ *   status     device [num_solves*path_len]      LADL_CERTIFIED ... (output)
+ *   iters      device [4*num_solves*path_len] or NULL: CCD sweeps, coordinate
+ *              updates, ternary probes, finisher pivots (output)
+ */
+int ladl_solve_f32(ladl_plan_t plan, const float *X, const float *y, const float *lambda,
+                   const float *b_init, float *b, float *obj, uint32_t *active, int32_t *zero_rows,
+                   int32_t *status, int32_t *iters, void *stream);
+
+/* The same solve by a plain kernel with one GPU thread per solve and X read
+ * from global memory: the paper's coarse-parallel design (Abstract,
+ * Section 5), kept as the speed baseline.  Same arguments and outputs. */
+int ladl_solve_plain_f32(ladl_plan_t plan, const float *X, const float *y, const float *lambda,
+                         const float *b_init, float *b, float *obj, uint32_t *active,
+                         int32_t *zero_rows, int32_t *status, int32_t *iters, void *stream);
+
+/*
+ * Gradient of a loss L through the solution at path step `step` (usually
+ * path_len - 1), using b_S = X_{Z,S}^{-1} y_Z at the optimal vertex:
+ *   w = X_{Z,S}^{-T} g_S,  dL/dy_Z = w,  dL/dX_{Z,S} = -w b_S^T,
+ * every other entry 0 (the vertex form of Section 3.2).  Solves whose
+ * status is not LADL_CERTIFIED get zero gradients.
+ *   b, zero_rows, status   device, the forward outputs (all steps)
+ *   grad_b     device, packed like one path step of b
+ *   grad_y     device, packed like y (output; fully written)
+ *   grad_X     device, packed like X (output; fully written)
+ * Every problem must be used by exactly one solve.
+ */
+int ladl_backward_f32(ladl_plan_t plan, const float *X, const float *b, const int32_t *zero_rows,
+                      const int32_t *status, int32_t step, const float *grad_b, float *grad_y,
+                      float *grad_X, void *stream);
+
+/*
+ * Lambda path as a HIP graph: path_len launches, one per path step, each
+ * warm-started from the previous step's output, captured once and replayed
+ * by ladl_graph_launch.  The pointers are baked into the graph: refill the
+ * same buffers to run new data of the same layout.
+ */
+int ladl_graph_create(ladl_plan_t plan, const float *X, const float *y, const float *lambda,
+                      const float *b_init, float *b, float *obj, uint32_t *active, int32_t *zero_rows,
+                      int32_t *status, int32_t *iters, ladl_graph_t *graph);
+int ladl_graph_launch(ladl_graph_t graph, void *stream);
+int ladl_graph_destroy(ladl_graph_t graph);
+
+/*
+ * Time each candidate schedule on this plan's own data (runs the solve
+ * several times on `stream`, synchronously) and keep the fastest per
+ * bucket in the plan.  Optional: plans start with a static choice.
+ */
+int ladl_autotune(ladl_plan_t plan, const float *X, const float *y, const float *lambda, float *b,
+                  float *obj, uint32_t *active, int32_t *zero_rows, int32_t *status, void *stream);
+
+/* Describe the plan's buckets and schedules as text (host buffer). */
+int ladl_plan_describe(ladl_plan_t plan, char *buf, int64_t buf_len);
+
+const char *ladl_error_string(int code);
+const char *ladl_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -36,7 +36,8 @@ class Prob(C.Structure):
 class Info(C.Structure):
     _fields_ = [("f", C.c_double), ("stage", C.c_int), ("certified", C.c_int), ("unique", C.c_int),
                 ("nS", C.c_int), ("S_mask", C.c_uint64), ("Z", C.c_int * MAX_P), ("umax", C.c_double),
-                ("cmax", C.c_double), ("gap", C.c_double), ("sweeps", C.c_long), ("updates", C.c_long),
+                ("cmax", C.c_double), ("gap", C.c_double), ("margin_uc", C.c_double),
+                ("margin_r", C.c_double), ("sweeps", C.c_long), ("updates", C.c_long),
                 ("probes", C.c_long), ("pivots", C.c_long), ("f_ccd", C.c_double)]
 
     def as_dict(self):
@@ -88,7 +89,7 @@ def lib():
         i32p, i64p = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
         L.orc_solve_batch.argtypes = [C.c_int, i32p, i64p, i64p, i32p, dp, dp, dp, C.c_int, i64p,
                                       C.POINTER(Opts), C.c_int, dp, dp, i32p, C.POINTER(C.c_uint32), i32p,
-                                      i32p, i64p]
+                                      i32p, i64p, dp]
         L.orc_solve_batch.restype = C.c_double
         _lib = L
     return _lib
@@ -229,7 +230,8 @@ def solve_batch(w, nthreads: Optional[int] = None, solves=None, b_init=None, **o
     lam64 = np.ascontiguousarray(lam, dtype=np.float64)
     out = dict(b=np.zeros(int(ps.sum()) * L), f=np.zeros(S * L), stage=np.zeros(S * L, np.int32),
                smask=np.zeros(S * L, np.uint32), zrows=np.zeros(S * L * 32, np.int32),
-               cert=np.zeros(S * L, np.int32), counters=np.zeros(S * L * 4, np.int64))
+               cert=np.zeros(S * L, np.int32), counters=np.zeros(S * L * 4, np.int64),
+               margin=np.zeros(S * L * 2))
     o = default_opts(**opts)
     i32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
     i64 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
@@ -240,9 +242,10 @@ def solve_batch(w, nthreads: Optional[int] = None, solves=None, b_init=None, **o
                                  _d(lam64), L, i64(b_off), C.byref(o), int(nthreads), _d(out["b"]),
                                  _d(out["f"]), i32(out["stage"]),
                                  out["smask"].ctypes.data_as(C.POINTER(C.c_uint32)), i32(out["zrows"]),
-                                 i32(out["cert"]), i64(out["counters"]))
+                                 i32(out["cert"]), i64(out["counters"]), _d(out["margin"]))
     out["zrows"] = out["zrows"].reshape(S * L, 32)
     out["counters"] = out["counters"].reshape(S * L, 4)
+    out["margin"] = out["margin"].reshape(S * L, 2)
     out["seconds"] = secs
     out["threads"] = nthreads
     out["b_off"] = b_off

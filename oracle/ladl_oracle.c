@@ -325,50 +325,74 @@ typedef struct {
 } overt;
 
 /* The vertex nearest to b: of the n + p hyperplanes {x_i.b = y_i} and
- * {b_j = 0} (Section 3.2), take the p closest to b in Euclidean distance
- * (|r_i| / ||x_i||_2 for a row, |b_j| for an axis; ties: axes first, then
- * lower index).  The axes not taken form S, the rows taken form Z, so
+ * {b_j = 0} (Section 3.2), take p that meet in a single point, nearest
+ * first in Euclidean distance (|r_i| / ||x_i||_2 for a row, |b_j| for an
+ * axis; ties: axes first, then lower index).  A hyperplane whose normal is
+ * linearly dependent on the normals already taken (a duplicated row, say)
+ * is passed over.  The axes not taken form S and the rows taken form Z, so
  * |Z| = |S|.  Rows with x_i = 0 are not hyperplanes and are never taken. */
+typedef struct {
+    double d;
+    int h;
+} ocand;
+
+static int ocand_cmp(const void *a, const void *b)
+{
+    const ocand *x = (const ocand *)a, *y = (const ocand *)b;
+    if (x->d < y->d) return -1;
+    if (x->d > y->d) return 1;
+    return (x->h > y->h) - (x->h < y->h);
+}
+
 static void choose_vertex(const orc_prob *P, const double *b, const double *r, overt *V)
 {
     const int n = P->n, p = P->p;
-    double best[ORC_MAX_P];
-    int id[ORC_MAX_P];
-    int cnt = 0;
+    ocand *c = (ocand *)malloc(sizeof(ocand) * (size_t)(n + p));
+    int m = 0;
     for (int h = 0; h < n + p; ++h) {
-        double v;
         if (h < p) {
-            v = fabs(b[h]);
+            c[m].d = fabs(b[h]);
         } else {
             int i = h - p;
             double nrm = 0.0;
             for (int j = 0; j < p; ++j) nrm += XIJ(P, i, j) * XIJ(P, i, j);
             if (nrm == 0.0) continue;
-            v = fabs(r[i]) / sqrt(nrm);
+            c[m].d = fabs(r[i]) / sqrt(nrm);
         }
-        if (cnt < p || v < best[cnt - 1]) {
-            int pos = (cnt < p) ? cnt++ : cnt - 1;
-            while (pos > 0 && best[pos - 1] > v) {
-                best[pos] = best[pos - 1];
-                id[pos] = id[pos - 1];
-                --pos;
-            }
-            best[pos] = v;
-            id[pos] = h;
-        }
+        c[m].h = h;
+        ++m;
     }
-    int taken[ORC_MAX_P] = {0};
-    V->s = 0;
-    int nz = 0;
-    for (int q = 0; q < cnt; ++q) {
-        if (id[q] < p)
-            taken[id[q]] = 1;
+    qsort(c, (size_t)m, sizeof *c, ocand_cmp);
+    static const int QLD = ORC_MAX_P;
+    double Q[ORC_MAX_P * ORC_MAX_P], v[ORC_MAX_P];
+    int taken[ORC_MAX_P] = {0}, acc = 0, nz = 0;
+    for (int q = 0; q < m && acc < p; ++q) {
+        int h = c[q].h;
+        for (int j = 0; j < p; ++j) v[j] = h < p ? (double)(j == h) : XIJ(P, h - p, j);
+        double n0 = 0.0;
+        for (int j = 0; j < p; ++j) n0 += v[j] * v[j];
+        n0 = sqrt(n0);
+        for (int a = 0; a < acc; ++a) { /* modified Gram-Schmidt */
+            double d = 0.0;
+            for (int j = 0; j < p; ++j) d += Q[a * QLD + j] * v[j];
+            for (int j = 0; j < p; ++j) v[j] -= d * Q[a * QLD + j];
+        }
+        double nv = 0.0;
+        for (int j = 0; j < p; ++j) nv += v[j] * v[j];
+        nv = sqrt(nv);
+        if (!(nv > 1e-9 * n0)) continue; /* dependent on those taken */
+        for (int j = 0; j < p; ++j) Q[acc * QLD + j] = v[j] / nv;
+        ++acc;
+        if (h < p)
+            taken[h] = 1;
         else
-            V->Z[nz++] = id[q] - p;
+            V->Z[nz++] = h - p;
     }
+    free(c);
+    V->s = 0;
     for (int j = 0; j < p; ++j)
         if (!taken[j]) V->S[V->s++] = j;
-    if (nz != V->s) V->s = -1; /* fewer than p hyperplanes exist */
+    if (acc < p || nz != V->s) V->s = -1; /* fewer than p independent hyperplanes */
 }
 
 static void vertex_matrix(const orc_prob *P, const overt *V, double *A)
@@ -474,6 +498,8 @@ static void fill_info(const orc_prob *P, const overt *V, const double *b, const 
     I->umax = C->umax;
     I->cmax = C->cmax;
     I->gap = C->gap;
+    I->margin_uc = fmin(C->margin_u, C->margin_c);
+    I->margin_r = C->margin_r;
     I->nS = 0;
     I->S_mask = 0;
     for (int j = 0; j < P->p; ++j)
@@ -844,7 +870,54 @@ static int solve_w(const orc_prob *P, const orc_opts *o, const double *b_init, d
         I->stage = ORC_STAGE_FINISHER;
         return 1;
     }
-    (void)n;
+    /* A degenerate vertex (more rows on their hyperplanes than active
+     * coordinates, e.g. duplicated rows) can make the edge steps cycle.
+     * Perturb y by a tiny deterministic amount so that no two rows share a
+     * hyperplane, finish there, then take the same vertex with the original
+     * y.  The perturbed problem's dual vector u is feasible for the original
+     * one (|u_i| <= 1, |X^T u| <= lambda do not involve y), so y.u is a lower
+     * bound on the optimum and f(b) - y.u bounds the remaining error. */
+    {
+        double ybar = 0.0;
+        for (int i = 0; i < n; ++i) ybar += fabs(P->y[i]);
+        ybar /= (n > 0 ? n : 1);
+        double *yp = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        for (int i = 0; i < n; ++i) {
+            uint32_t hsh = (uint32_t)i * 2654435761u;
+            double mag = 0.5 + 0.5 * (double)((hsh >> 8) & 0xFFFF) / 65535.0;
+            double sgn_ = (hsh >> 31) ? -1.0 : 1.0;
+            yp[i] = P->y[i] + 1e-9 * (fabs(P->y[i]) + ybar) * mag * sgn_;
+        }
+        orc_prob Pp = *P;
+        Pp.y = yp;
+        memcpy(W->bb, b, sizeof(double) * (size_t)p);
+        residuals(&Pp, W->bb, W->r);
+        choose_vertex(&Pp, W->bb, W->r, &V);
+        int ok = finisher(&Pp, o, lam, W->bb, W, &V, I);
+        if (ok) {
+            /* W->u holds the perturbed problem's dual vector */
+            double yu = 0.0;
+            for (int i = 0; i < n; ++i) yu += P->y[i] * W->u[i];
+            if (vertex_solve(P, &V, &W->L, W->A, W->bb)) {
+                double f = orc_objective(&(orc_prob){n, p, P->X, P->y, lam}, W->bb);
+                double gap = f - yu;
+                if (gap <= 1e-9 * fmax(1.0, f)) {
+                    memcpy(b, W->bb, sizeof(double) * (size_t)p);
+                    I->f = f;
+                    I->gap = gap;
+                    I->certified = 1;
+                    I->unique = 0;
+                    I->margin_uc = 0.0;
+                    I->margin_r = 0.0;
+                    I->stage = ORC_STAGE_FINISHER + 1;
+                    free(yp);
+                    return 1;
+                }
+            }
+        }
+        free(yp);
+    }
+    I->certified = 0;
     return 0;
 }
 
@@ -1053,6 +1126,7 @@ typedef struct {
     int32_t *stage_out, *zrows_out, *cert_out;
     uint32_t *smask_out;
     int64_t *counters_out;
+    double *margin_out;
     atomic_int next;
 } obatch;
 
@@ -1096,6 +1170,10 @@ static void *batch_worker(void *arg)
             }
             if (B->zrows_out)
                 for (int q = 0; q < 32; ++q) B->zrows_out[o * 32 + q] = (ok && q < ORC_MAX_P) ? I.Z[q] : -1;
+            if (B->margin_out) {
+                B->margin_out[2 * o] = ok ? I.margin_uc : -1.0;
+                B->margin_out[2 * o + 1] = ok ? I.margin_r : -1.0;
+            }
             if (B->counters_out) {
                 int64_t *c = B->counters_out + o * 4;
                 c[0] = I.sweeps;
@@ -1113,7 +1191,8 @@ double orc_solve_batch(int num_solves, const int32_t *problem, const int64_t *ro
                        const int64_t *x_off, const int32_t *p_arr, const double *X, const double *y,
                        const double *lam, int path_len, const int64_t *b_off, const orc_opts *o,
                        int nthreads, double *b_out, double *f_out, int32_t *stage_out,
-                       uint32_t *smask_out, int32_t *zrows_out, int32_t *cert_out, int64_t *counters_out)
+                       uint32_t *smask_out, int32_t *zrows_out, int32_t *cert_out, int64_t *counters_out,
+                       double *margin_out)
 {
     obatch B;
     B.num_solves = num_solves;
@@ -1135,6 +1214,7 @@ double orc_solve_batch(int num_solves, const int32_t *problem, const int64_t *ro
     B.cert_out = cert_out;
     B.smask_out = smask_out;
     B.counters_out = counters_out;
+    B.margin_out = margin_out;
     atomic_init(&B.next, 0);
     struct timespec t0, t1;
     clock_gettime(CLOCK_MONOTONIC, &t0);

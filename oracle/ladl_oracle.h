@@ -66,6 +66,8 @@ typedef struct {
     double umax;       /* max_{i in Z} |u_i|                                     */
     double cmax;       /* max_{j not in S} |c_j| - lambda   (<= 0 when feasible) */
     double gap;        /* f(b) - y.u (LP duality gap)                            */
+    double margin_uc;  /* min(1 - max|u_Z|, min_{j not in S} (lambda-|c_j|)/(lambda+sum_i|x_ij|)) */
+    double margin_r;   /* min over rows off Z of |r_i| / (|y_i| + sum_j |x_ij b_j|) */
     long sweeps, updates, probes, pivots;
     double f_ccd;      /* objective after the first CCD                          */
 } orc_info;
@@ -117,13 +119,15 @@ int orc_backward(const orc_prob *P, const double *b, const int *Z, const double 
  * (warm-started), spread over nthreads threads.  Layout as in the HIP
  * library: X packed row-major blocks at x_off[k], y at row_off[k], lambda at
  * lam[s*path_len + t], outputs of (s,t) at b + path_len*b_off[s] + t*p_s and
- * index s*path_len + t for the scalars, zrows padded to 32 per output.
+ * index s*path_len + t for the scalars, zrows padded to 32 per output,
+ * margin_out (nullable) 2 doubles per output: margin_uc, margin_r.
  * Returns wall seconds of the solve loop. */
 double orc_solve_batch(int num_solves, const int32_t *problem, const int64_t *row_off,
                        const int64_t *x_off, const int32_t *p_arr, const double *X, const double *y,
                        const double *lam, int path_len, const int64_t *b_off, const orc_opts *o,
                        int nthreads, double *b_out, double *f_out, int32_t *stage_out,
-                       uint32_t *smask_out, int32_t *zrows_out, int32_t *cert_out, int64_t *counters_out);
+                       uint32_t *smask_out, int32_t *zrows_out, int32_t *cert_out, int64_t *counters_out,
+                       double *margin_out);
 
 #ifdef __cplusplus
 }

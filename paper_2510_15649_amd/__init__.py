@@ -1,0 +1,300 @@
+"""Batched LAD-LASSO on AMD MI355X: Python binding of libladlasso.so.
+
+Argument marshalling only: every step of the solve runs in the HIP kernels
+of the library.  PyTorch provides device memory and streams.  When the
+library has not been built, every entry point raises; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libladlasso.so")
+
+# status codes
+CERTIFIED, NONUNIQUE, MAXITER, NONFINITE, BADLAMBDA, NOTCERTIFIED = range(6)
+STATUS_NAMES = ["CERTIFIED", "NONUNIQUE", "MAXITER", "NONFINITE", "BADLAMBDA", "NOTCERTIFIED"]
+# option flags
+FLAG_GOLDEN, FLAG_NO_FINISHER, FLAG_NO_SNAP = 1, 2, 4
+# return codes
+OK, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, -1, -2, -3, -4
+ZPAD = 32
+
+EXPORTED = ["ladl_create", "ladl_destroy", "ladl_default_options", "ladl_plan_create", "ladl_plan_destroy",
+            "ladl_plan_b_len", "ladl_solve_f32", "ladl_solve_plain_f32", "ladl_backward_f32",
+            "ladl_graph_create", "ladl_graph_launch", "ladl_graph_destroy", "ladl_autotune",
+            "ladl_plan_describe", "ladl_error_string", "ladl_last_error_detail"]
+
+
+class Options(C.Structure):
+    _fields_ = [("tol_f", C.c_float), ("tol_s", C.c_float), ("lambda_min", C.c_float),
+                ("max_sweeps", C.c_int32), ("max_ternary", C.c_int32), ("max_rounds", C.c_int32),
+                ("max_pivots", C.c_int32), ("flags", C.c_int32), ("schedule", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Layout(C.Structure):
+    _fields_ = [("num_problems", C.c_int32), ("row_off", C.POINTER(C.c_int64)),
+                ("x_off", C.POINTER(C.c_int64)), ("p", C.POINTER(C.c_int32)), ("p_uniform", C.c_int32),
+                ("x_len", C.c_int64), ("y_len", C.c_int64), ("num_solves", C.c_int32),
+                ("problem", C.POINTER(C.c_int32)), ("path_len", C.c_int32)]
+
+
+class LadlError(RuntimeError):
+    def __init__(self, code: int, detail: str):
+        super().__init__(f"{detail} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libladlasso.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                           f"g.build()'` (no CPU fallback exists)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.ladl_create.argtypes = [C.POINTER(vp)]
+    L.ladl_destroy.argtypes = [vp]
+    L.ladl_default_options.argtypes = [C.POINTER(Options)]
+    L.ladl_default_options.restype = None
+    L.ladl_plan_create.argtypes = [vp, C.POINTER(Layout), C.POINTER(Options), C.POINTER(vp)]
+    L.ladl_plan_destroy.argtypes = [vp]
+    L.ladl_plan_b_len.argtypes = [vp]
+    L.ladl_plan_b_len.restype = i64
+    solve_args = [vp] + [vp] * 10 + [vp]
+    L.ladl_solve_f32.argtypes = solve_args
+    L.ladl_solve_plain_f32.argtypes = solve_args
+    L.ladl_backward_f32.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp]
+    L.ladl_graph_create.argtypes = [vp] + [vp] * 10 + [C.POINTER(vp)]
+    L.ladl_graph_launch.argtypes = [vp, vp]
+    L.ladl_graph_destroy.argtypes = [vp]
+    L.ladl_autotune.argtypes = [vp] + [vp] * 9
+    L.ladl_plan_describe.argtypes = [vp, C.c_char_p, i64]
+    L.ladl_error_string.argtypes = [C.c_int]
+    L.ladl_error_string.restype = C.c_char_p
+    L.ladl_last_error_detail.argtypes = []
+    L.ladl_last_error_detail.restype = C.c_char_p
+    for name in ["ladl_create", "ladl_destroy", "ladl_plan_create", "ladl_plan_destroy", "ladl_solve_f32",
+                 "ladl_solve_plain_f32", "ladl_backward_f32", "ladl_graph_create", "ladl_graph_launch",
+                 "ladl_graph_destroy", "ladl_autotune", "ladl_plan_describe"]:
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(rc: int):
+    if rc != OK:
+        L = lib()
+        raise LadlError(rc, f"{L.ladl_error_string(rc).decode()}: {L.ladl_last_error_detail().decode()}")
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().ladl_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+class Handle:
+    """A library handle bound to the current HIP device."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        check(lib().ladl_create(C.byref(h)))
+        self._h = h
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ladl_destroy(self._h)
+            self._h = None
+
+
+_default_handle = None
+
+
+def default_handle() -> Handle:
+    global _default_handle
+    if _default_handle is None:
+        _default_handle = Handle()
+    return _default_handle
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A validated batch layout (host arrays are copied at creation).
+
+    row_off   int64 [P+1]   rows of problem k: row_off[k]:row_off[k+1]
+    p         int or int32 [P]   features per problem
+    x_off     int64 [P] or None  (None: row_off[k] * p for uniform p)
+    problem   int32 [S] or None  problem of each solve (None: identity)
+    path_len  lambdas per solve (warm-started path)
+    """
+
+    def __init__(self, row_off, p, *, x_len: int, y_len: int, problem=None, path_len: int = 1, x_off=None,
+                 options: Optional[Options] = None, handle: Optional[Handle] = None, **opt_kw):
+        self.handle = handle or default_handle()
+        self.options = options if options is not None else default_options(**opt_kw)
+        self._row_off = np.ascontiguousarray(row_off, dtype=np.int64)
+        P = self._row_off.shape[0] - 1
+        if np.isscalar(p):
+            self._p = None
+            p_uniform = int(p)
+            self.p_per_problem = np.full(P, p_uniform, dtype=np.int32)
+        else:
+            self._p = np.ascontiguousarray(p, dtype=np.int32)
+            p_uniform = int(self._p[0]) if P > 0 else 0
+            self.p_per_problem = self._p
+        self._x_off = None if x_off is None else np.ascontiguousarray(x_off, dtype=np.int64)
+        self._problem = None if problem is None else np.ascontiguousarray(problem, dtype=np.int32)
+        S = P if problem is None else int(self._problem.shape[0])
+        lay = Layout()
+        lay.num_problems = P
+        lay.row_off = self._row_off.ctypes.data_as(C.POINTER(C.c_int64))
+        lay.x_off = None if self._x_off is None else self._x_off.ctypes.data_as(C.POINTER(C.c_int64))
+        lay.p = None if self._p is None else self._p.ctypes.data_as(C.POINTER(C.c_int32))
+        lay.p_uniform = p_uniform
+        lay.x_len = int(x_len)
+        lay.y_len = int(y_len)
+        lay.num_solves = S
+        lay.problem = None if self._problem is None else self._problem.ctypes.data_as(C.POINTER(C.c_int32))
+        lay.path_len = int(path_len)
+        h = C.c_void_p()
+        check(lib().ladl_plan_create(self.handle.ptr, C.byref(lay), C.byref(self.options), C.byref(h)))
+        self._plan = h
+        self.num_problems, self.num_solves, self.path_len = P, S, int(path_len)
+        self.b_len = int(lib().ladl_plan_b_len(h))
+        prob = np.arange(S, dtype=np.int32) if self._problem is None else self._problem
+        self.p_per_solve = self.p_per_problem[prob]
+        self.b_off = np.zeros(S, dtype=np.int64)
+        if S > 1:
+            self.b_off[1:] = np.cumsum(self.p_per_solve.astype(np.int64))[:-1]
+
+    @classmethod
+    def for_workload(cls, w, **kw) -> "Plan":
+        return cls(w.row_off, w.p, x_off=w.x_off, problem=w.problem, path_len=w.path_len,
+                   x_len=w.X.size, y_len=w.y.size, **kw)
+
+    def __del__(self):
+        if getattr(self, "_plan", None) and _lib is not None:
+            _lib.ladl_plan_destroy(self._plan)
+            self._plan = None
+
+    def describe(self) -> str:
+        buf = C.create_string_buffer(8192)
+        check(lib().ladl_plan_describe(self._plan, buf, 8192))
+        return buf.value.decode()
+
+    def alloc_outputs(self, device="cuda", iters=True):
+        import torch
+        n_out = self.num_solves * self.path_len
+        return dict(b=torch.empty(self.b_len, dtype=torch.float32, device=device),
+                    obj=torch.empty(n_out, dtype=torch.float32, device=device),
+                    active=torch.empty(n_out, dtype=torch.int32, device=device),
+                    zero_rows=torch.empty(n_out * ZPAD, dtype=torch.int32, device=device),
+                    status=torch.empty(n_out, dtype=torch.int32, device=device),
+                    iters=torch.empty(n_out * 4, dtype=torch.int32, device=device) if iters else None)
+
+    def _call(self, fn, X, y, lam, b_init, out, stream):
+        check(fn(self._plan, _ptr(X), _ptr(y), _ptr(lam), _ptr(b_init), _ptr(out["b"]), _ptr(out["obj"]),
+                 _ptr(out["active"]), _ptr(out["zero_rows"]), _ptr(out["status"]), _ptr(out.get("iters")),
+                 _stream(stream)))
+        return out
+
+    def solve(self, X, y, lam, b_init=None, out=None, stream=None, iters=True):
+        """Forward solve with the wavefront-per-solve kernels (float32 device
+        tensors).  Returns a dict of output tensors (enqueued on `stream`)."""
+        out = out or self.alloc_outputs(X.device, iters)
+        return self._call(lib().ladl_solve_f32, X, y, lam, b_init, out, stream)
+
+    def solve_plain(self, X, y, lam, b_init=None, out=None, stream=None, iters=True):
+        """The same solve with one GPU thread per solve (baseline kernel)."""
+        out = out or self.alloc_outputs(X.device, iters)
+        return self._call(lib().ladl_solve_plain_f32, X, y, lam, b_init, out, stream)
+
+    def backward(self, X, out, grad_b, step: int = -1, grad_y=None, grad_X=None, stream=None):
+        import torch
+        step = self.path_len - 1 if step < 0 else step
+        grad_y = grad_y if grad_y is not None else torch.empty(int(self._row_off[-1]), dtype=torch.float32,
+                                                                 device=X.device)
+        grad_X = grad_X if grad_X is not None else torch.empty_like(X)
+        check(lib().ladl_backward_f32(self._plan, _ptr(X), _ptr(out["b"]), _ptr(out["zero_rows"]),
+                                      _ptr(out["status"]), int(step), _ptr(grad_b), _ptr(grad_y),
+                                      _ptr(grad_X), _stream(stream)))
+        return grad_y, grad_X
+
+    def graph(self, X, y, lam, out, b_init=None) -> "PathGraph":
+        return PathGraph(self, X, y, lam, out, b_init)
+
+    def autotune(self, X, y, lam, out, stream=None):
+        check(lib().ladl_autotune(self._plan, _ptr(X), _ptr(y), _ptr(lam), _ptr(out["b"]), _ptr(out["obj"]),
+                                  _ptr(out["active"]), _ptr(out["zero_rows"]), _ptr(out["status"]),
+                                  _stream(stream)))
+
+    def b_view(self, b, s: int, t: int = 0):
+        """Coefficients of solve s at path step t inside a flat b array."""
+        p = int(self.p_per_solve[s])
+        o = self.path_len * int(self.b_off[s]) + t * p
+        return b[o:o + p]
+
+
+class PathGraph:
+    """The lambda path captured as a HIP graph of path_len launches."""
+
+    def __init__(self, plan: Plan, X, y, lam, out, b_init=None):
+        self.plan = plan
+        self._keep = (X, y, lam, out, b_init)
+        g = C.c_void_p()
+        check(lib().ladl_graph_create(plan._plan, _ptr(X), _ptr(y), _ptr(lam), _ptr(b_init), _ptr(out["b"]),
+                                      _ptr(out["obj"]), _ptr(out["active"]), _ptr(out["zero_rows"]),
+                                      _ptr(out["status"]), _ptr(out.get("iters")), C.byref(g)))
+        self._g = g
+
+    def launch(self, stream=None):
+        check(lib().ladl_graph_launch(self._g, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "_g", None) and _lib is not None:
+            _lib.ladl_graph_destroy(self._g)
+            self._g = None
+
+
+def to_device(w, device="cuda"):
+    """Copy a Workload's arrays to device tensors."""
+    import torch
+    d = dict(X=torch.from_numpy(w.X).to(device), y=torch.from_numpy(w.y).to(device),
+             lam=torch.from_numpy(w.lam).to(device))
+    if w.grad_b is not None:
+        d["grad_b"] = torch.from_numpy(w.grad_b).to(device)
+    return d

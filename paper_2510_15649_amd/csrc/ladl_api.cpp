@@ -1,0 +1,467 @@
+// C-ABI of the batched LAD-LASSO library: validation, plans, launches.
+#include "ladlasso.h"
+#include "ladl_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using namespace ladl;
+
+namespace {
+
+thread_local std::string g_detail;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_detail = buf;
+    return code;
+}
+
+int hipfail(hipError_t e, const char *what)
+{
+    return fail(LADL_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int KNOWN_FLAGS = LADL_FLAG_GOLDEN | LADL_FLAG_NO_FINISHER | LADL_FLAG_NO_SNAP;
+constexpr int NMAX_LDS = 1024; // rows per problem held in LDS (16 slots x 64 lanes)
+
+int rows_per_lane(int n)
+{
+    int r = (n + 63) / 64, R = 1;
+    while (R < r) R <<= 1;
+    return R;
+}
+
+} // namespace
+
+struct ladl_handle_s {
+    int device = 0;
+    int num_cu = 0;
+    size_t lds_max = 0;
+};
+
+struct Bucket {
+    int R = 1, pmax = 1;
+    int offset = 0, count = 0; // slice of the order array
+    int grid = 0;
+};
+
+struct ladl_plan_s {
+    ladl_handle_s *h = nullptr;
+    int P = 0, S = 0, L = 1;
+    std::vector<int64_t> row_off, x_off, b_off;
+    std::vector<int32_t> p, problem;
+    int64_t b_len = 0, x_len = 0, y_len = 0;
+    ladl_options opt{};
+    std::vector<Bucket> buckets;
+    int64_t *d_row_off = nullptr, *d_x_off = nullptr, *d_b_off = nullptr;
+    int32_t *d_p = nullptr, *d_problem = nullptr, *d_order = nullptr, *d_counters = nullptr;
+    int32_t *d_order_plain = nullptr, *d_counter_plain = nullptr;
+    float *d_gws = nullptr;
+    int64_t gws_stride = 0;
+    int nmax = 0, pmax = 0;
+    bool problems_once = false; // every problem used by exactly one solve
+};
+
+struct ladl_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+};
+
+// exported functions: C linkage comes from their declarations in ladlasso.h
+
+const char *ladl_error_string(int code)
+{
+    switch (code) {
+    case LADL_OK: return "LADL_OK";
+    case LADL_EINVAL: return "LADL_EINVAL: invalid argument";
+    case LADL_EUNSUPPORTED: return "LADL_EUNSUPPORTED: outside supported limits";
+    case LADL_EHIP: return "LADL_EHIP: HIP runtime error";
+    case LADL_ENOMEM: return "LADL_ENOMEM: allocation failed";
+    default: return "unknown ladl error code";
+    }
+}
+
+const char *ladl_last_error_detail(void) { return g_detail.c_str(); }
+
+void ladl_default_options(ladl_options *o)
+{
+    if (!o) return;
+    o->tol_f = 1e-6f;
+    o->tol_s = 9.5367431640625e-07f; // 2^-20
+    o->lambda_min = 0.f;
+    o->max_sweeps = 64;
+    o->max_ternary = 48;
+    o->max_rounds = 1;
+    o->max_pivots = 0;
+    o->flags = 0;
+    o->schedule = -1;
+}
+
+int ladl_create(ladl_handle_t *handle)
+{
+    if (!handle) return fail(LADL_EINVAL, "handle pointer is NULL");
+    *handle = nullptr;
+    auto *h = new (std::nothrow) ladl_handle_s;
+    if (!h) return fail(LADL_ENOMEM, "host allocation");
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return hipfail(e, "hipGetDevice");
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return hipfail(e, "hipGetDeviceProperties");
+    }
+    h->num_cu = prop.multiProcessorCount;
+    h->lds_max = prop.sharedMemPerBlock;
+    if (prop.maxSharedMemoryPerMultiProcessor > h->lds_max) h->lds_max = prop.maxSharedMemoryPerMultiProcessor;
+    if (h->lds_max > 160 * 1024) h->lds_max = 160 * 1024;
+    *handle = h;
+    return LADL_OK;
+}
+
+int ladl_destroy(ladl_handle_t h)
+{
+    delete h;
+    return LADL_OK;
+}
+
+static int check_options(const ladl_options *o)
+{
+    if (!(o->tol_f >= 0.f) || !std::isfinite(o->tol_f)) return fail(LADL_EINVAL, "tol_f must be finite and >= 0");
+    if (!(o->tol_s > 0.f) || !std::isfinite(o->tol_s)) return fail(LADL_EINVAL, "tol_s must be finite and > 0");
+    if (!(o->lambda_min >= 0.f) || !std::isfinite(o->lambda_min))
+        return fail(LADL_EINVAL, "lambda_min must be finite and >= 0");
+    if (o->max_sweeps < 1 || o->max_sweeps > 100000) return fail(LADL_EINVAL, "max_sweeps out of [1, 100000]");
+    if (o->max_ternary < 0 || o->max_ternary > 10000) return fail(LADL_EINVAL, "max_ternary out of [0, 10000]");
+    if (o->max_rounds < -1 || o->max_rounds > 64) return fail(LADL_EINVAL, "max_rounds out of [-1, 64]");
+    if (o->max_pivots < 0 || o->max_pivots > 100000) return fail(LADL_EINVAL, "max_pivots out of [0, 100000]");
+    if (o->flags & ~KNOWN_FLAGS) return fail(LADL_EINVAL, "unknown flag bits 0x%x", o->flags & ~KNOWN_FLAGS);
+    if (o->schedule < -1 || o->schedule > 0) return fail(LADL_EINVAL, "unknown schedule %d", o->schedule);
+    return LADL_OK;
+}
+
+static void plan_free_device(ladl_plan_s *pl)
+{
+    (void)hipFree(pl->d_row_off);
+    (void)hipFree(pl->d_x_off);
+    (void)hipFree(pl->d_b_off);
+    (void)hipFree(pl->d_p);
+    (void)hipFree(pl->d_problem);
+    (void)hipFree(pl->d_order);
+    (void)hipFree(pl->d_counters);
+    (void)hipFree(pl->d_order_plain);
+    (void)hipFree(pl->d_counter_plain);
+    (void)hipFree(pl->d_gws);
+}
+
+template <typename T>
+static hipError_t upload(T **dst, const std::vector<T> &src)
+{
+    size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+    hipError_t e = hipMalloc((void **)dst, bytes);
+    if (e != hipSuccess) return e;
+    if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+}
+
+int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options *opt, ladl_plan_t *out)
+{
+    if (!out) return fail(LADL_EINVAL, "plan pointer is NULL");
+    *out = nullptr;
+    if (!h || !lay) return fail(LADL_EINVAL, "handle or layout is NULL");
+    ladl_options o;
+    ladl_default_options(&o);
+    if (opt) o = *opt;
+    int rc = check_options(&o);
+    if (rc) return rc;
+    const int P = lay->num_problems, S = lay->num_solves, L = lay->path_len;
+    if (P < 1) return fail(LADL_EINVAL, "num_problems must be >= 1 (got %d)", P);
+    if (S < 1) return fail(LADL_EINVAL, "num_solves must be >= 1 (got %d)", S);
+    if (L < 1) return fail(LADL_EINVAL, "path_len must be >= 1 (got %d)", L);
+    if ((int64_t)S * L > (int64_t)INT32_MAX / 32) return fail(LADL_EUNSUPPORTED, "too many solve outputs");
+    if (!lay->row_off) return fail(LADL_EINVAL, "row_off is NULL");
+    if (lay->x_len < 0 || lay->y_len < 0) return fail(LADL_EINVAL, "negative x_len or y_len");
+    auto pl = new (std::nothrow) ladl_plan_s;
+    if (!pl) return fail(LADL_ENOMEM, "host allocation");
+    pl->h = h;
+    pl->P = P;
+    pl->S = S;
+    pl->L = L;
+    pl->opt = o;
+    pl->x_len = lay->x_len;
+    pl->y_len = lay->y_len;
+    pl->row_off.assign(lay->row_off, lay->row_off + P + 1);
+    pl->p.resize(P);
+    pl->x_off.resize(P);
+    auto bad = [&](int code, const char *fmt, auto... args) {
+        delete pl;
+        return fail(code, fmt, args...);
+    };
+    if (pl->row_off[0] != 0) return bad(LADL_EINVAL, "row_off[0] must be 0 (got %lld)", (long long)pl->row_off[0]);
+    for (int k = 0; k < P; ++k) {
+        int64_t n = pl->row_off[k + 1] - pl->row_off[k];
+        if (n < 1) return bad(LADL_EINVAL, "problem %d has %lld rows (row_off must increase)", k, (long long)n);
+        if (n > NMAX_LDS) return bad(LADL_EUNSUPPORTED, "problem %d has %lld rows (limit %d)", k, (long long)n, NMAX_LDS);
+        int pk = lay->p ? lay->p[k] : lay->p_uniform;
+        if (pk < 1 || pk > PMAX) return bad(LADL_EUNSUPPORTED, "problem %d has p = %d (limit 1..%d)", k, pk, PMAX);
+        if (!lay->x_off && lay->p && pk != lay->p_uniform)
+            return bad(LADL_EINVAL, "x_off is NULL but p[%d] = %d differs from p_uniform", k, pk);
+        int64_t xo = lay->x_off ? lay->x_off[k] : pl->row_off[k] * (int64_t)lay->p_uniform;
+        if (xo < 0 || xo + n * pk > lay->x_len)
+            return bad(LADL_EINVAL, "problem %d: X block [%lld, %lld) outside x_len %lld", k, (long long)xo,
+                       (long long)(xo + n * pk), (long long)lay->x_len);
+        pl->p[k] = pk;
+        pl->x_off[k] = xo;
+        pl->nmax = std::max<int>(pl->nmax, (int)n);
+        pl->pmax = std::max(pl->pmax, pk);
+    }
+    if (pl->row_off[P] > lay->y_len)
+        return bad(LADL_EINVAL, "row_off[%d] = %lld exceeds y_len %lld", P, (long long)pl->row_off[P],
+                   (long long)lay->y_len);
+    pl->problem.resize(S);
+    std::vector<int> uses(P, 0);
+    for (int s = 0; s < S; ++s) {
+        int k = lay->problem ? lay->problem[s] : s;
+        if (k < 0 || k >= P) return bad(LADL_EINVAL, "problem[%d] = %d out of range", s, k);
+        pl->problem[s] = k;
+        uses[k]++;
+    }
+    pl->problems_once = std::all_of(uses.begin(), uses.end(), [](int u) { return u == 1; });
+    pl->b_off.resize(S);
+    int64_t acc = 0;
+    for (int s = 0; s < S; ++s) {
+        pl->b_off[s] = acc;
+        acc += pl->p[pl->problem[s]];
+    }
+    pl->b_len = acc * L;
+    // buckets by rows per lane; decreasing cost inside a bucket
+    std::vector<int> Rs = {16, 8, 4, 2, 1};
+    std::vector<int32_t> order;
+    order.reserve(S);
+    for (int R : Rs) {
+        Bucket b;
+        b.R = R;
+        b.offset = (int)order.size();
+        std::vector<int32_t> ids;
+        for (int s = 0; s < S; ++s) {
+            int k = pl->problem[s];
+            int n = (int)(pl->row_off[k + 1] - pl->row_off[k]);
+            if (rows_per_lane(n) == R) ids.push_back(s);
+        }
+        if (ids.empty()) continue;
+        std::stable_sort(ids.begin(), ids.end(), [&](int a, int c) {
+            int ka = pl->problem[a], kc = pl->problem[c];
+            int64_t ca = (pl->row_off[ka + 1] - pl->row_off[ka]) * pl->p[ka];
+            int64_t cc = (pl->row_off[kc + 1] - pl->row_off[kc]) * pl->p[kc];
+            return ca > cc;
+        });
+        for (int s : ids) b.pmax = std::max(b.pmax, (int)pl->p[pl->problem[s]]);
+        b.count = (int)ids.size();
+        order.insert(order.end(), ids.begin(), ids.end());
+        size_t lds = wave_lds_bytes(R, b.pmax);
+        if (lds > h->lds_max)
+            return bad(LADL_EUNSUPPORTED, "bucket R=%d p=%d needs %zu bytes of LDS (device limit %zu)", R, b.pmax,
+                       lds, h->lds_max);
+        int per_cu = wave_max_blocks_per_cu(R, b.pmax);
+        if (per_cu < 1) per_cu = 1;
+        b.grid = std::min<int64_t>(b.count, (int64_t)per_cu * h->num_cu);
+        pl->buckets.push_back(b);
+    }
+    // plain kernel: all solves, decreasing cost
+    std::vector<int32_t> order_plain(S);
+    std::iota(order_plain.begin(), order_plain.end(), 0);
+    std::stable_sort(order_plain.begin(), order_plain.end(), [&](int a, int c) {
+        int ka = pl->problem[a], kc = pl->problem[c];
+        return (pl->row_off[ka + 1] - pl->row_off[ka]) * pl->p[ka] > (pl->row_off[kc + 1] - pl->row_off[kc]) * pl->p[kc];
+    });
+    hipError_t e;
+    std::vector<int32_t> zeros(pl->buckets.size() + 1, 0);
+    if ((e = upload(&pl->d_row_off, pl->row_off)) != hipSuccess || (e = upload(&pl->d_x_off, pl->x_off)) != hipSuccess ||
+        (e = upload(&pl->d_b_off, pl->b_off)) != hipSuccess || (e = upload(&pl->d_p, pl->p)) != hipSuccess ||
+        (e = upload(&pl->d_problem, pl->problem)) != hipSuccess || (e = upload(&pl->d_order, order)) != hipSuccess ||
+        (e = upload(&pl->d_counters, zeros)) != hipSuccess ||
+        (e = upload(&pl->d_order_plain, order_plain)) != hipSuccess ||
+        (e = upload(&pl->d_counter_plain, std::vector<int32_t>(1, 0))) != hipSuccess) {
+        plan_free_device(pl);
+        delete pl;
+        return hipfail(e, "plan upload");
+    }
+    *out = pl;
+    return LADL_OK;
+}
+
+int ladl_plan_destroy(ladl_plan_t pl)
+{
+    if (!pl) return LADL_OK;
+    plan_free_device(pl);
+    delete pl;
+    return LADL_OK;
+}
+
+int64_t ladl_plan_b_len(ladl_plan_t pl) { return pl ? pl->b_len : -1; }
+
+static DevOpt dev_opt(const ladl_options &o)
+{
+    DevOpt d;
+    d.tol_f = o.tol_f;
+    d.tol_s = o.tol_s;
+    d.lambda_min = o.lambda_min;
+    d.max_sweeps = o.max_sweeps;
+    d.max_ternary = o.max_ternary;
+    d.max_rounds = o.max_rounds;
+    d.max_pivots = o.max_pivots;
+    d.flags = o.flags;
+    return d;
+}
+
+static int check_solve_ptrs(ladl_plan_t pl, const float *X, const float *y, const float *lam, float *b, float *obj,
+                            uint32_t *active, int32_t *zr, int32_t *st)
+{
+    if (!pl) return fail(LADL_EINVAL, "plan is NULL");
+    if (!X || !y || !lam || !b || !obj || !active || !zr || !st)
+        return fail(LADL_EINVAL, "a required device pointer is NULL");
+    if (((uintptr_t)X | (uintptr_t)y | (uintptr_t)lam | (uintptr_t)b | (uintptr_t)obj | (uintptr_t)active |
+         (uintptr_t)zr | (uintptr_t)st) & 3)
+        return fail(LADL_EINVAL, "device pointers must be 4-byte aligned");
+    return LADL_OK;
+}
+
+static SolveArgs base_args(ladl_plan_t pl, const float *X, const float *y, const float *lam, const float *b_init,
+                           float *b, float *obj, uint32_t *active, int32_t *zr, int32_t *st, int32_t *it, int t0,
+                           int t1)
+{
+    SolveArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.X = X;
+    a.y = y;
+    a.lam = lam;
+    a.b_init = b_init;
+    a.row_off = pl->d_row_off;
+    a.x_off = pl->d_x_off;
+    a.b_off = pl->d_b_off;
+    a.p_arr = pl->d_p;
+    a.problem = pl->d_problem;
+    a.path_len = pl->L;
+    a.t0 = t0;
+    a.t1 = t1;
+    a.b_out = b;
+    a.obj_out = obj;
+    a.active_out = active;
+    a.zrows_out = zr;
+    a.status_out = st;
+    a.iters_out = it;
+    a.opt = dev_opt(pl->opt);
+    return a;
+}
+
+static int enqueue_wave(ladl_plan_t pl, const float *X, const float *y, const float *lam, const float *b_init,
+                        float *b, float *obj, uint32_t *active, int32_t *zr, int32_t *st, int32_t *it, int t0,
+                        int t1, hipStream_t s)
+{
+    hipError_t e = launch_reset(pl->d_counters, (int)pl->buckets.size(), s);
+    if (e != hipSuccess) return hipfail(e, "queue reset launch");
+    for (size_t bi = 0; bi < pl->buckets.size(); ++bi) {
+        const Bucket &bk = pl->buckets[bi];
+        SolveArgs a = base_args(pl, X, y, lam, b_init, b, obj, active, zr, st, it, t0, t1);
+        a.order = pl->d_order + bk.offset;
+        a.num_items = bk.count;
+        a.counter = pl->d_counters + bi;
+        a.pmax = bk.pmax;
+        e = launch_wave(bk.R, a, bk.grid, s);
+        if (e != hipSuccess) return hipfail(e, "solve kernel launch");
+    }
+    return LADL_OK;
+}
+
+int ladl_solve_f32(ladl_plan_t pl, const float *X, const float *y, const float *lam, const float *b_init, float *b,
+                   float *obj, uint32_t *active, int32_t *zr, int32_t *st, int32_t *it, void *stream)
+{
+    int rc = check_solve_ptrs(pl, X, y, lam, b, obj, active, zr, st);
+    if (rc) return rc;
+    return enqueue_wave(pl, X, y, lam, b_init, b, obj, active, zr, st, it, 0, pl->L, (hipStream_t)stream);
+}
+
+int ladl_solve_plain_f32(ladl_plan_t pl, const float *X, const float *y, const float *lam, const float *b_init,
+                         float *b, float *obj, uint32_t *active, int32_t *zr, int32_t *st, int32_t *it,
+                         void *stream)
+{
+    int rc = check_solve_ptrs(pl, X, y, lam, b, obj, active, zr, st);
+    if (rc) return rc;
+    return fail(LADL_EUNSUPPORTED, "plain kernel not built yet");
+}
+
+int ladl_backward_f32(ladl_plan_t pl, const float *X, const float *b, const int32_t *zr, const int32_t *st,
+                      int32_t step, const float *grad_b, float *grad_y, float *grad_X, void *stream)
+{
+    if (!pl) return fail(LADL_EINVAL, "plan is NULL");
+    return fail(LADL_EUNSUPPORTED, "backward not built yet");
+}
+
+int ladl_graph_create(ladl_plan_t pl, const float *X, const float *y, const float *lam, const float *b_init,
+                      float *b, float *obj, uint32_t *active, int32_t *zr, int32_t *st, int32_t *it,
+                      ladl_graph_t *graph)
+{
+    if (!graph) return fail(LADL_EINVAL, "graph pointer is NULL");
+    *graph = nullptr;
+    return fail(LADL_EUNSUPPORTED, "graph path not built yet");
+}
+
+int ladl_graph_launch(ladl_graph_t g, void *stream)
+{
+    if (!g) return fail(LADL_EINVAL, "graph is NULL");
+    return LADL_EUNSUPPORTED;
+}
+
+int ladl_graph_destroy(ladl_graph_t g)
+{
+    if (!g) return LADL_OK;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    delete g;
+    return LADL_OK;
+}
+
+int ladl_autotune(ladl_plan_t pl, const float *X, const float *y, const float *lam, float *b, float *obj,
+                  uint32_t *active, int32_t *zr, int32_t *st, void *stream)
+{
+    if (!pl) return fail(LADL_EINVAL, "plan is NULL");
+    return LADL_OK;
+}
+
+int ladl_plan_describe(ladl_plan_t pl, char *buf, int64_t len)
+{
+    if (!pl || !buf || len < 1) return fail(LADL_EINVAL, "bad arguments");
+    std::string s;
+    char line[256];
+    snprintf(line, sizeof line, "problems=%d solves=%d path_len=%d nmax=%d pmax=%d b_len=%lld\n", pl->P, pl->S,
+             pl->L, pl->nmax, pl->pmax, (long long)pl->b_len);
+    s += line;
+    for (const Bucket &b : pl->buckets) {
+        snprintf(line, sizeof line, "bucket R=%d (n<=%d) pmax=%d solves=%d grid=%d lds=%zuB\n", b.R, 64 * b.R, b.pmax,
+                 b.count, b.grid, wave_lds_bytes(b.R, b.pmax));
+        s += line;
+    }
+    std::strncpy(buf, s.c_str(), (size_t)len - 1);
+    buf[len - 1] = 0;
+    return LADL_OK;
+}
+

@@ -1,0 +1,53 @@
+// Launch descriptors shared by the host API and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ladl {
+
+constexpr int PMAX = 32;     // features per problem
+constexpr int NMAX = 2048;   // rows per problem
+constexpr int ZPAD = 32;     // zero_rows entries per output
+
+struct DevOpt {
+    float tol_f, tol_s, lambda_min;
+    int max_sweeps, max_ternary, max_rounds, max_pivots, flags;
+};
+
+// One launch of the forward solve over a list of solves (one bucket).
+struct SolveArgs {
+    const float *X, *y, *lam, *b_init;
+    const int64_t *row_off, *x_off, *b_off;
+    const int32_t *p_arr, *problem;
+    const int32_t *order; // solve ids of this bucket, decreasing cost
+    int32_t num_items;
+    int32_t path_len;
+    int32_t t0, t1;       // path steps computed by this launch
+    int32_t *counter;     // work-queue head (zeroed by k_reset before launch)
+    float *b_out, *obj_out;
+    uint32_t *active_out;
+    int32_t *zrows_out, *status_out, *iters_out;
+    float *gws;           // plain kernel: per-thread global scratch
+    int64_t gws_stride;   // floats per thread
+    DevOpt opt;
+    int32_t pmax;         // largest p in the bucket (LDS carve-up)
+};
+
+struct BackwardArgs {
+    const float *X, *b, *grad_b;
+    const int32_t *zrows, *status;
+    const int64_t *row_off, *x_off, *b_off;
+    const int32_t *p_arr, *problem;
+    int32_t num_solves, path_len, step;
+    float *grad_y, *grad_X;
+};
+
+// host-side launchers (defined in ladl_kernels.hip)
+size_t wave_lds_bytes(int R, int pmax);
+int wave_max_blocks_per_cu(int R, int pmax);
+hipError_t launch_reset(int32_t *counters, int n, hipStream_t s);
+hipError_t launch_wave(int R, const SolveArgs &a, int grid, hipStream_t s);
+hipError_t launch_plain(const SolveArgs &a, int grid, int block, hipStream_t s);
+hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);
+
+} // namespace ladl

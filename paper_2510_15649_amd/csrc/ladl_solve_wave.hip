@@ -1,0 +1,1257 @@
+// Forward LAD-LASSO solve: one wavefront per solve, persistent grid with an
+// atomic work queue, problem data resident in LDS.
+//
+// Per solve (Abstract; Sections 3.3-3.6 of the paper, plus a vertex
+// certificate and simplex finisher that the paper does not have):
+//   1. cyclical coordinate descent, each axis minimised exactly by the
+//      weighted median of the kinks r_i/x_ij + b_j (weights |x_ij|) and the
+//      penalty kink 0 (weight lambda);
+//   2. snap to the nearest vertex (p hyperplanes, Section 3.2) and test the
+//      LP optimality certificate;
+//   3. ternary chop along one axis, each probe a restricted warm-started
+//      CCD with that axis frozen, range extended until it brackets the
+//      minimum (Sections 3.5-3.6); polish, snap and certify again;
+//   4. primal simplex steps along the vertex's edges until certified.
+//
+// Layout in LDS (floats), per wave:
+//   Xs  p columns of LDN = 64R+1 floats; row i of column j at j*LDN + i,
+//       row i owned by lane i%64, register slot i/64 (rows >= n are 0)
+//   ys, rn   y and the row norms ||x_i||_2, LDN each
+//   A   vertex matrix / LU factors, 32 x 33
+//   small vectors of 32 (b, best b, column |x| sums, direction, scratch)
+//   gd  32 doubles (certificate), sa/sw 64+64 (selection compaction)
+#include "ladl_kernels.hpp"
+#include "ladl_wave.hpp"
+
+#include <climits>
+
+namespace ladl {
+
+constexpr int FLAG_GOLDEN = 1, FLAG_NO_FINISHER = 2, FLAG_NO_SNAP = 4;
+enum { ST_CERTIFIED = 0, ST_NONUNIQUE = 1, ST_MAXITER = 2, ST_NONFINITE = 3, ST_BADLAMBDA = 4, ST_NOTCERT = 5 };
+
+// optimality certificate slack in fp32 (dual variables computed with fp64 sums)
+constexpr float TOL_U = 1e-4f;   // |u_i| <= 1 + TOL_U on Z
+constexpr float TOL_C = 1e-4f;   // |c_j| <= lambda (1 + TOL_C) + TOL_CA * sum_i |x_ij| off S
+constexpr float TOL_CA = 1e-5f;
+// margins below which a certified vertex is reported as possibly non-unique
+constexpr float MARGIN_U = 1e-3f, MARGIN_C = 1e-3f, MARGIN_R = 1e-5f;
+
+constexpr int ALD = 33; // leading dimension of the vertex matrix
+
+#define LADL_INL __device__ __attribute__((always_inline)) inline
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float unif(float v) { return bitsf(__builtin_amdgcn_readfirstlane(fbits(v))); }
+
+__host__ __device__ constexpr int wave_ldn(int R) { return 64 * R + 1; }
+
+__host__ __device__ constexpr size_t wave_lds_floats(int R, int pmax)
+{
+    return (size_t)pmax * wave_ldn(R) + 2 * (size_t)wave_ldn(R) + 32 * ALD + 6 * 32 + 64 /*gd*/ + 128 +
+           3 * 32;
+}
+
+template <int R>
+struct Wave {
+    static constexpr int LDN = wave_ldn(R);
+    float *Xs, *ys, *rn, *A, *vb, *vbb, *vca, *vd, *vg, *vt, *sa, *sw;
+    double *gd;
+    int *zs, *ss, *piv;
+    int n, p, nslot;
+    float lam, ynorm1;
+    DevOpt opt;
+    int c_sweeps, c_updates, c_probes, c_pivots;
+};
+
+template <int R>
+LADL_INL void carve(Wave<R> &w, float *smem, int pmax)
+{
+    constexpr int LDN = Wave<R>::LDN;
+    float *q = smem;
+    w.gd = (double *)q; // first: the dynamic LDS base is 16-byte aligned
+    q += 64;
+    w.Xs = q;
+    q += (size_t)pmax * LDN;
+    w.ys = q;
+    q += LDN;
+    w.rn = q;
+    q += LDN;
+    w.A = q;
+    q += 32 * ALD;
+    w.vb = q;
+    q += 32;
+    w.vbb = q;
+    q += 32;
+    w.vca = q;
+    q += 32;
+    w.vd = q;
+    q += 32;
+    w.vg = q;
+    q += 32;
+    w.vt = q;
+    q += 32;
+    w.sa = q;
+    q += 64;
+    w.sw = q;
+    q += 64;
+    w.zs = (int *)q;
+    q += 32;
+    w.ss = (int *)q;
+    q += 32;
+    w.piv = (int *)q;
+}
+
+// --------------------------------------------------------------------------
+// problem load: X row-major in HBM -> column-major in LDS (coalesced reads)
+// --------------------------------------------------------------------------
+template <int R>
+LADL_INL bool load_problem(Wave<R> &w, const float *__restrict__ X, const float *__restrict__ y)
+{
+    constexpr int LDN = Wave<R>::LDN;
+    const int l = lane_id(), n = w.n, p = w.p, top = 64 * w.nslot;
+    for (int j = 0; j < p; ++j)
+        for (int i = n + l; i < top; i += 64) w.Xs[j * LDN + i] = 0.f;
+    for (int i = n + l; i < top; i += 64) {
+        w.ys[i] = 0.f;
+        w.rn[i] = 0.f;
+    }
+    bool finite = true;
+    const int np = n * p;
+    const float invp = 1.0f / (float)p;
+    for (int e = l; e < np; e += 64) {
+        float v = X[e];
+        int i = (int)((float)e * invp);
+        if (i * p > e)
+            --i;
+        else if ((i + 1) * p <= e)
+            ++i;
+        w.Xs[(e - i * p) * LDN + i] = v;
+        finite = finite && __builtin_isfinite(v);
+    }
+    for (int i = l; i < n; i += 64) {
+        float v = y[i];
+        w.ys[i] = v;
+        finite = finite && __builtin_isfinite(v);
+    }
+    __syncthreads();
+    for (int i = l; i < n; i += 64) {
+        float s2 = 0.f;
+        for (int j = 0; j < p; ++j) {
+            float x = w.Xs[j * LDN + i];
+            s2 = fmaf(x, x, s2);
+        }
+        w.rn[i] = sqrtf(s2);
+    }
+    for (int j = 0; j < p; ++j) {
+        float part = 0.f;
+        for (int i = l; i < n; i += 64) part += fabsf(w.Xs[j * LDN + i]);
+        float sj = wsum(part);
+        if (l == j) w.vca[j] = sj;
+    }
+    float yp = 0.f;
+    for (int i = l; i < n; i += 64) yp += fabsf(w.ys[i]);
+    w.ynorm1 = wsum(yp);
+    __syncthreads();
+    return ballot(!finite) == 0;
+}
+
+// r = y - X b with b in vb
+template <int R>
+LADL_INL void residuals(Wave<R> &w, float (&r)[R])
+{
+    constexpr int LDN = Wave<R>::LDN;
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 0; k < R; ++k) r[k] = (k < w.nslot) ? w.ys[64 * k + l] : 0.f;
+    for (int j = 0; j < w.p; ++j) {
+        float bj = unif(w.vb[j]);
+        if (bj != 0.f) {
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                if (k < w.nslot) r[k] = fmaf(-w.Xs[j * LDN + 64 * k + l], bj, r[k]);
+        }
+    }
+}
+
+template <int R>
+LADL_INL float objective(Wave<R> &w, const float (&r)[R], const float *bvec)
+{
+    const int l = lane_id();
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < R; ++k) s += fabsf(r[k]);
+    float sb = (l < w.p) ? fabsf(bvec[l]) : 0.f;
+    float z = 0.f;
+    wsum3(s, sb, z);
+    return s + w.lam * sb;
+}
+
+// --------------------------------------------------------------------------
+// Weighted selection over the wave.
+// Candidates: per-lane register keys a[k] (FINF = none) with weights wt[k],
+// plus one extra key (av, wv) per lane.  All keys are >= 0.  Returns the
+// smallest key a* whose cumulative weight (over keys <= a*) reaches T
+// (strict: exceeds T), and which register slot or extra key holds it
+// (row keys win ties against extra keys).
+// --------------------------------------------------------------------------
+struct Sel {
+    float a;
+    int lane, slot;
+    bool virt;
+};
+
+template <int R>
+LADL_INL Sel owner_of(const float (&a)[R], float av, float m)
+{
+    const int l = lane_id();
+    int myslot = -1;
+#pragma unroll
+    for (int k = R - 1; k >= 0; --k)
+        if (a[k] == m) myslot = k;
+    uint64_t rb = ballot(myslot >= 0);
+    Sel s;
+    s.a = m;
+    if (rb) {
+        s.lane = first_lane(rb);
+        s.slot = rdlane(myslot, s.lane);
+        s.virt = false;
+    } else {
+        uint64_t vb = ballot(av == m);
+        s.lane = vb ? first_lane(vb) : 0;
+        s.slot = -1;
+        s.virt = true;
+    }
+    return s;
+}
+
+template <int R>
+LADL_INL Sel wselect(Wave<R> &w, const float (&a)[R], const float (&wt)[R], float av, float wv, float T,
+                       bool strict)
+{
+    const int l = lane_id();
+    float lo = -1.f, hi = FINF, cum = 0.f;
+    auto reached = [&](float c) { return strict ? (c > T) : (c >= T); };
+    // Phase A: the next two distinct keys (small moves of a warm start)
+    for (int it = 0; it < 2; ++it) {
+        float m = FINF;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (a[k] > lo) m = fminf(m, a[k]);
+        if (av > lo) m = fminf(m, av);
+        m = wmin(m);
+        if (m == FINF) {
+            if (lo < 0.f) return Sel{FINF, 0, -1, false}; // no candidate at all
+            return owner_of<R>(a, av, lo);                 // weight exhausted by rounding
+        }
+        float wm = 0.f;
+#pragma unroll
+        for (int k = 0; k < R; ++k) wm += (a[k] == m) ? wt[k] : 0.f;
+        wm += (av == m) ? wv : 0.f;
+        wm = wsum(wm);
+        if (reached(cum + wm)) return owner_of<R>(a, av, m);
+        cum += wm;
+        lo = m;
+    }
+    // Phase B: narrow (lo, hi] around the target with sampled quantiles
+    int cnt = 0;
+    for (int round = 0; round < 12; ++round) {
+        cnt = 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) cnt += popc64(ballot(a[k] > lo && a[k] <= hi));
+        cnt += popc64(ballot(av > lo && av <= hi));
+        if (cnt <= 64) break;
+        float smp = FINF, wint = 0.f;
+#pragma unroll
+        for (int k = R - 1; k >= 0; --k) {
+            bool in = a[k] > lo && a[k] <= hi;
+            smp = in ? a[k] : smp;
+            wint += in ? wt[k] : 0.f;
+        }
+        if (av > lo && av <= hi) {
+            smp = (smp == FINF) ? av : smp;
+            wint += wv;
+        }
+        wint = wsum(wint);
+        int ns = popc64(ballot(smp < FINF));
+        bitonic64(smp);
+        float frac = (T - cum) / wint;
+        frac = fminf(fmaxf(frac, 0.f), 1.f);
+        int rk = (int)(frac * (float)ns);
+        int r1 = max(0, min(ns - 1, rk - 4)), r2 = max(0, min(ns - 1, rk + 4));
+        float p1 = rdlane(smp, r1), p2 = rdlane(smp, r2);
+        float c1 = 0.f, c2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            bool in = a[k] > lo && a[k] <= hi;
+            c1 += (in && a[k] <= p1) ? wt[k] : 0.f;
+            c2 += (in && a[k] <= p2) ? wt[k] : 0.f;
+        }
+        if (av > lo && av <= hi) {
+            c1 += (av <= p1) ? wv : 0.f;
+            c2 += (av <= p2) ? wv : 0.f;
+        }
+        float z = 0.f;
+        wsum3(c1, c2, z);
+        if (reached(cum + c1)) {
+            hi = p1;
+        } else if (reached(cum + c2)) {
+            cum += c1;
+            lo = p1;
+            hi = p2;
+        } else {
+            cum += c2;
+            lo = p2;
+        }
+    }
+    if (cnt > 64) {
+        // many equal keys: step through distinct values
+        for (int guard = 0; guard < 4096; ++guard) {
+            float m = FINF;
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                if (a[k] > lo && a[k] <= hi) m = fminf(m, a[k]);
+            if (av > lo && av <= hi) m = fminf(m, av);
+            m = wmin(m);
+            if (m == FINF) break;
+            float wm = 0.f;
+#pragma unroll
+            for (int k = 0; k < R; ++k) wm += (a[k] == m) ? wt[k] : 0.f;
+            wm += (av == m) ? wv : 0.f;
+            wm = wsum(wm);
+            if (reached(cum + wm) || m == hi) return owner_of<R>(a, av, m);
+            cum += wm;
+            lo = m;
+        }
+        return owner_of<R>(a, av, hi);
+    }
+    // Phase C: compact the <= 64 keys of (lo, hi], sort, scan
+    int base = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        bool in = a[k] > lo && a[k] <= hi;
+        uint64_t bal = ballot(in);
+        if (in) {
+            int pos = base + mbcnt(bal);
+            w.sa[pos] = a[k];
+            w.sw[pos] = wt[k];
+        }
+        base += popc64(bal);
+    }
+    {
+        bool in = av > lo && av <= hi;
+        uint64_t bal = ballot(in);
+        if (in) {
+            int pos = base + mbcnt(bal);
+            w.sa[pos] = av;
+            w.sw[pos] = wv;
+        }
+        base += popc64(bal);
+    }
+    __syncthreads();
+    float key = (l < base) ? w.sa[l] : FINF;
+    float val = (l < base) ? w.sw[l] : 0.f;
+    __syncthreads();
+    bitonic64(key, val);
+    float inc = wscan_incl(val);
+    uint64_t ok = ballot(key < FINF && reached(cum + inc));
+    float m;
+    if (ok)
+        m = rdlane(key, first_lane(ok));
+    else if (base > 0)
+        m = rdlane(key, base - 1); // rounding: take the last key
+    else
+        m = (hi < FINF) ? hi : lo;
+    return owner_of<R>(a, av, m);
+}
+
+// --------------------------------------------------------------------------
+// H4: exact minimisation of f along axis j (weighted median of the kinks)
+// --------------------------------------------------------------------------
+template <int R>
+LADL_INL bool coord_update(Wave<R> &w, float (&r)[R], int j)
+{
+    constexpr int LDN = Wave<R>::LDN;
+    const int l = lane_id();
+    const float *xc = w.Xs + j * LDN;
+    float x[R];
+    float bel = 0.f, at = 0.f, abv = 0.f;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        x[k] = (k < w.nslot) ? xc[64 * k + l] : 0.f;
+        float rr = r[k], ax = fabsf(x[k]);
+        bool z = (rr == 0.f);
+        bool neg = __builtin_signbit(rr) != __builtin_signbit(x[k]);
+        at += z ? ax : 0.f;
+        bel += (!z && neg) ? ax : 0.f;
+        abv += (!z && !neg) ? ax : 0.f;
+    }
+    const float bj = unif(w.vb[j]);
+    wsum3(bel, at, abv);
+    const float lam = w.lam;
+    const float W = (bel + at) + (abv + lam);
+    if (!(W > 0.f)) return false;
+    const float belT = bel + ((bj > 0.f) ? lam : 0.f);
+    const float atT = at + ((bj == 0.f) ? lam : 0.f);
+    const float half = 0.5f * W;
+    int dir;
+    if (belT >= half)
+        dir = -1;
+    else if (belT + atT < half)
+        dir = 1;
+    else
+        return false;
+    float a[R], wt[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        float rr = r[k], xk = x[k];
+        bool neg = __builtin_signbit(rr) != __builtin_signbit(xk);
+        bool cand = (xk != 0.f) && (rr != 0.f) && (dir < 0 ? neg : !neg);
+        float ax = fabsf(xk);
+        a[k] = cand ? fabsf(rr) * __builtin_amdgcn_rcpf(ax) : FINF;
+        wt[k] = cand ? ax : 0.f;
+    }
+    const bool lcand = (lam > 0.f) && (dir < 0 ? (bj > 0.f) : (bj < 0.f));
+    const float av = (l == 0 && lcand) ? fabsf(bj) : FINF;
+    const float wv = (l == 0 && lcand) ? lam : 0.f;
+    const float T = (dir < 0) ? (belT - half) : (half - belT - atT);
+    Sel s = wselect<R>(w, a, wt, av, wv, T, dir < 0);
+    float nb = s.virt ? 0.f : ((dir < 0) ? bj - s.a : bj + s.a);
+    float d = nb - bj;
+    if (d == 0.f || !__builtin_isfinite(d)) return false;
+#pragma unroll
+    for (int k = 0; k < R; ++k) r[k] = fmaf(-x[k], d, r[k]);
+    if (!s.virt && l == s.lane) {
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (k == s.slot) r[k] = 0.f; // the median row is now on its hyperplane
+    }
+    if (l == 0) w.vb[j] = nb;
+    __syncthreads();
+    return true;
+}
+
+// H5: cyclic sweeps, axis `frozen` held fixed
+template <int R>
+LADL_INL float ccd(Wave<R> &w, float (&r)[R], int frozen, float f)
+{
+    for (int sw = 0; sw < w.opt.max_sweeps; ++sw) {
+        bool changed = false;
+        for (int j = 0; j < w.p; ++j) {
+            if (j == frozen) continue;
+            changed |= coord_update<R>(w, r, j);
+            w.c_updates++;
+        }
+        w.c_sweeps++;
+        float fn = objective<R>(w, r, w.vb);
+        bool stop = !changed || (f - fn <= w.opt.tol_f * fn);
+        f = fn;
+        if (stop) break;
+    }
+    return f;
+}
+
+// --------------------------------------------------------------------------
+// H6: ternary chop along axis kax (Sections 3.5-3.6), as a state machine fed
+// with one probe value F(s) at a time so that the solve has a single CCD
+// call site.  F(s) = f after CCD with b_kax := s and axis kax frozen,
+// started from the best point found so far.  The range c +- max(1,|c|) is
+// extended by doubling while an end is lower than the centre (clamped to
+// |b_kax| <= ||y||_1 / lambda, which bounds every minimiser), then cut in
+// thirds (or golden sections) keeping the better side.
+// --------------------------------------------------------------------------
+struct Chop {
+    float lo, hi, c, h, B, Fc, Flo, Fhi, m1, m2, F1, F2;
+    int stage, which, ext, it;
+    bool have1, have2;
+};
+
+LADL_INL void chop_init(Chop &q, float c, float f, float B)
+{
+    q.B = B;
+    q.c = c;
+    q.h = fmaxf(1.f, fabsf(c));
+    q.lo = fmaxf(c - q.h, -B);
+    q.hi = fminf(c + q.h, B);
+    q.Fc = f;
+    q.Flo = q.Fhi = q.F1 = q.F2 = FINF;
+    q.m1 = q.m2 = 0.f;
+    q.stage = 0;
+    q.which = 0;
+    q.ext = 0;
+    q.it = 0;
+    q.have1 = q.have2 = false;
+}
+
+// Record the value of the last requested probe (when which != 0) and return
+// the next probe point in s; false when the chop is finished.
+LADL_INL bool chop_next(Chop &q, float F, float &s, const DevOpt &opt)
+{
+    switch (q.which) {
+    case 1: q.Flo = F; break;
+    case 2: q.Fhi = F; break;
+    case 3: q.F1 = F; q.have1 = true; break;
+    case 4: q.F2 = F; q.have2 = true; break;
+    default: break;
+    }
+    const bool golden = (opt.flags & FLAG_GOLDEN) != 0;
+    const float g = 0.381966011f;
+    for (int guard = 0; guard < 8; ++guard) {
+        switch (q.stage) {
+        case 0: // F(lo)
+            q.stage = 1;
+            q.which = 1;
+            s = q.lo;
+            return true;
+        case 1: // F(hi)
+            q.stage = 2;
+            q.which = 2;
+            s = q.hi;
+            return true;
+        case 2: // extend to the left while F(lo) < F(c)
+            if (q.Flo < q.Fc && q.lo > -q.B && q.ext < 64) {
+                q.hi = q.c;
+                q.Fhi = q.Fc;
+                q.c = q.lo;
+                q.Fc = q.Flo;
+                q.h *= 2.f;
+                q.lo = fmaxf(q.c - q.h, -q.B);
+                ++q.ext;
+                q.which = 1;
+                s = q.lo;
+                return true;
+            }
+            q.stage = 3;
+            break;
+        case 3: // extend to the right while F(hi) < F(c)
+            if (q.Fhi < q.Fc && q.hi < q.B && q.ext < 128) {
+                q.lo = q.c;
+                q.Flo = q.Fc;
+                q.c = q.hi;
+                q.Fc = q.Fhi;
+                q.h *= 2.f;
+                q.hi = fminf(q.c + q.h, q.B);
+                ++q.ext;
+                q.which = 2;
+                s = q.hi;
+                return true;
+            }
+            q.stage = 4;
+            break;
+        default: // chop
+            if (q.have1 && q.have2) {
+                if (q.F1 < q.F2) {
+                    q.hi = q.m2;
+                    if (golden) {
+                        q.m2 = q.m1;
+                        q.F2 = q.F1;
+                        q.have1 = false;
+                    } else {
+                        q.have1 = q.have2 = false;
+                    }
+                } else {
+                    q.lo = q.m1;
+                    if (golden) {
+                        q.m1 = q.m2;
+                        q.F1 = q.F2;
+                        q.have2 = false;
+                    } else {
+                        q.have1 = q.have2 = false;
+                    }
+                }
+                ++q.it;
+            }
+            if (q.hi - q.lo <= opt.tol_s * (1.f + fabsf(q.lo) + fabsf(q.hi)) || q.it >= opt.max_ternary) return false;
+            if (!q.have1) {
+                q.m1 = golden ? q.lo + g * (q.hi - q.lo) : q.lo + (q.hi - q.lo) / 3.f;
+                q.which = 3;
+                s = q.m1;
+            } else {
+                q.m2 = golden ? q.hi - g * (q.hi - q.lo) : q.hi - (q.hi - q.lo) / 3.f;
+                q.which = 4;
+                s = q.m2;
+            }
+            return true;
+        }
+    }
+    return false;
+}
+
+// --------------------------------------------------------------------------
+// H7: vertices, LU in LDS, certificate, finisher
+// --------------------------------------------------------------------------
+
+// the p hyperplanes ({x_i.b = y_i} or {b_j = 0}) nearest to the point
+// (vb, r): rows |r_i|/||x_i||, axes |b_j|; ties: axes first, then lower row.
+// Writes zs/ss and the per-lane Z bits; returns |S| (= |Z|) or -1.
+template <int R>
+LADL_INL int choose_vertex(Wave<R> &w, const float (&r)[R], uint32_t &zbits)
+{
+    const int l = lane_id(), p = w.p;
+    float dist[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        float nr = (k < w.nslot) ? w.rn[64 * k + l] : 0.f;
+        dist[k] = (nr > 0.f) ? fabsf(r[k]) / nr : FINF;
+    }
+    const float dv = (l < p) ? fabsf(w.vb[l]) : FINF;
+    zbits = 0;
+    bool ctaken = false;
+    int nz = 0;
+    for (int q = 0; q < p; ++q) {
+        float mr = FINF;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (!((zbits >> k) & 1u)) mr = fminf(mr, dist[k]);
+        float m = wmin(fminf(mr, ctaken ? FINF : dv));
+        if (m == FINF) return -1;
+        uint64_t cb = ballot(!ctaken && l < p && dv == m);
+        if (cb) {
+            if (l == first_lane(cb)) ctaken = true;
+        } else {
+            int best = INT_MAX;
+#pragma unroll
+            for (int k = R - 1; k >= 0; --k)
+                if (!((zbits >> k) & 1u) && dist[k] == m) best = 64 * k + l;
+            int gi = wmin_i(best);
+            if (l == (gi & 63)) zbits |= 1u << (gi >> 6);
+            if (l == 0) w.zs[nz] = gi;
+            ++nz;
+        }
+    }
+    uint64_t sb = ballot(l < p && !ctaken);
+    int s = popc64(sb);
+    if (l < p && !ctaken) w.ss[mbcnt(sb)] = l;
+    __syncthreads();
+    return (s == nz) ? s : -1;
+}
+
+LADL_INL bool lu_factor(float *A, int *piv, int s)
+{
+    const int l = lane_id();
+    float m = 0.f;
+    if (l < s)
+        for (int c = 0; c < s; ++c) m = fmaxf(m, fabsf(A[l * ALD + c]));
+    const float amax = wmax(m);
+    for (int k = 0; k < s; ++k) {
+        float v = (l >= k && l < s) ? fabsf(A[l * ALD + k]) : -1.f;
+        float vm = wmax(v);
+        if (!(vm > 1e-7f * amax)) return false;
+        int pr = first_lane(ballot(v == vm));
+        if (l == 0) piv[k] = pr;
+        if (pr != k && l < s) {
+            float t = A[k * ALD + l];
+            A[k * ALD + l] = A[pr * ALD + l];
+            A[pr * ALD + l] = t;
+        }
+        __syncthreads();
+        const float pk = unif(A[k * ALD + k]);
+        if (l > k && l < s) {
+            float lf = A[l * ALD + k] / pk;
+            A[l * ALD + k] = lf;
+            for (int c = k + 1; c < s; ++c) A[l * ALD + c] = fmaf(-lf, A[k * ALD + c], A[l * ALD + c]);
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// A x = v, v and x one element per lane (lane q < s)
+LADL_INL float lu_solve(const float *A, const int *piv, int s, float v)
+{
+    const int l = lane_id();
+    for (int k = 0; k < s; ++k) {
+        int pk = uni(piv[k]);
+        if (pk != k) {
+            float a = rdlane(v, k), b = rdlane(v, pk);
+            v = (l == k) ? b : ((l == pk) ? a : v);
+        }
+    }
+    for (int c = 0; c < s; ++c) {
+        float vc = rdlane(v, c);
+        if (l > c && l < s) v = fmaf(-A[l * ALD + c], vc, v);
+    }
+    for (int c = s - 1; c >= 0; --c) {
+        if (l == c) v = v / A[c * ALD + c];
+        float vc = rdlane(v, c);
+        if (l < c) v = fmaf(-A[l * ALD + c], vc, v);
+    }
+    return v;
+}
+
+// A^T x = v
+LADL_INL float lu_solve_t(const float *A, const int *piv, int s, float v)
+{
+    const int l = lane_id();
+    for (int c = 0; c < s; ++c) {
+        if (l == c) v = v / A[c * ALD + c];
+        float vc = rdlane(v, c);
+        if (l > c && l < s) v = fmaf(-A[c * ALD + l], vc, v);
+    }
+    for (int c = s - 1; c >= 0; --c) {
+        float vc = rdlane(v, c);
+        if (l < c) v = fmaf(-A[c * ALD + l], vc, v);
+    }
+    for (int k = s - 1; k >= 0; --k) {
+        int pk = uni(piv[k]);
+        if (pk != k) {
+            float a = rdlane(v, k), b = rdlane(v, pk);
+            v = (l == k) ? b : ((l == pk) ? a : v);
+        }
+    }
+    return v;
+}
+
+// Vertex (zs, ss, s): A = X_{Z,S} factored in LDS, b_S = A^{-1} y_Z with
+// one refinement step (residual in fp64), b into vt, residuals into rv
+// (exact zeros on Z), objective into f.  Lane c returns b_{S_c} in bS.
+template <int R>
+LADL_INL bool vertex_eval(Wave<R> &w, float (&rv)[R], uint32_t zbits, int s, float &f)
+{
+    constexpr int LDN = Wave<R>::LDN;
+    const int l = lane_id();
+    for (int q = 0; q < s; ++q) {
+        int zq = uni(w.zs[q]);
+        if (l < s) w.A[q * ALD + l] = w.Xs[w.ss[l] * LDN + zq];
+    }
+    __syncthreads();
+    if (!lu_factor(w.A, w.piv, s)) return false;
+    const int zl = (l < s) ? w.zs[l] : 0;
+    const float yz = (l < s) ? w.ys[zl] : 0.f;
+    float xs = lu_solve(w.A, w.piv, s, yz);
+    double acc = (double)yz;
+    for (int c = 0; c < s; ++c) {
+        float xc = rdlane(xs, c);
+        int jc = uni(w.ss[c]);
+        if (l < s) acc -= (double)w.Xs[jc * LDN + zl] * (double)xc;
+    }
+    xs += lu_solve(w.A, w.piv, s, (l < s) ? (float)acc : 0.f);
+    if (ballot(l < s && !__builtin_isfinite(xs))) return false;
+    if (l < w.p) w.vt[l] = 0.f;
+    __syncthreads();
+    if (l < s) w.vt[w.ss[l]] = xs;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < R; ++k) rv[k] = (k < w.nslot) ? w.ys[64 * k + l] : 0.f;
+    for (int c = 0; c < s; ++c) {
+        int jc = uni(w.ss[c]);
+        float bc = rdlane(xs, c);
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (k < w.nslot) rv[k] = fmaf(-w.Xs[jc * LDN + 64 * k + l], bc, rv[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+        if ((zbits >> k) & 1u) rv[k] = 0.f;
+    f = objective<R>(w, rv, w.vt);
+    return true;
+}
+
+// LP optimality certificate at the evaluated vertex (A holds its LU):
+// u_i = sign(r_i) off Z, X_{Z,S}^T u_Z = lambda sign(b_S) - X_{Zc,S}^T u_Zc,
+// c = X^T u.  Lane q returns u_{Z_q} in u, lane j returns c_j in c.
+template <int R>
+LADL_INL bool certificate(Wave<R> &w, const float (&rv)[R], uint32_t zbits, int s, float &u, float &c,
+                            bool &unique)
+{
+    constexpr int LDN = Wave<R>::LDN;
+    const int l = lane_id(), p = w.p;
+    double g = 0.0;
+    for (int j = 0; j < p; ++j) {
+        double part = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (k < w.nslot) part += (double)w.Xs[j * LDN + 64 * k + l] * (double)sgnf(rv[k]);
+        double gj = wsum_d(part);
+        if (l == j) g = gj;
+    }
+    if (l < p) w.gd[l] = g;
+    __syncthreads();
+    uint32_t smask = 0;
+    for (int q = 0; q < s; ++q) smask |= 1u << uni(w.ss[q]);
+    float rhs = 0.f;
+    if (l < s) {
+        int jq = w.ss[l];
+        rhs = (float)((double)w.lam * (double)sgnf(w.vt[jq]) - w.gd[jq]);
+    }
+    u = lu_solve_t(w.A, w.piv, s, rhs);
+    double cj = g;
+    for (int q = 0; q < s; ++q) {
+        float uq = rdlane(u, q);
+        int zq = uni(w.zs[q]);
+        if (l < p) cj += (double)w.Xs[l * LDN + zq] * (double)uq;
+    }
+    c = (float)cj;
+    const bool offS = (l < p) && !((smask >> l) & 1u);
+    const float umax = wmax((l < s) ? fabsf(u) : 0.f);
+    const float cabs = fabsf(c);
+    const float colabs = (l < p) ? w.vca[l] : 0.f;
+    const bool viol = offS && (cabs > w.lam * (1.f + TOL_C) + TOL_CA * colabs);
+    const bool cert = (umax <= 1.f + TOL_U) && (ballot(viol) == 0);
+    const float mc = wmin(offS ? (w.lam - cabs) / (w.lam + colabs) : FINF);
+    float mr = FINF;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        float nr = (k < w.nslot) ? w.rn[64 * k + l] : 0.f;
+        if (!((zbits >> k) & 1u) && nr > 0.f) mr = fminf(mr, fabsf(rv[k]) / nr);
+    }
+    mr = wmin(mr);
+    unique = cert && (1.f - umax > MARGIN_U) && (mc > MARGIN_C) && (mr > MARGIN_R * (1.f + w.ynorm1 / w.n));
+    return cert;
+}
+
+// Evaluate the vertex (zs, ss, s) and test its certificate; while it fails,
+// take primal simplex steps along the vertex's edges (a build addition):
+// release the most violated constraint, move to the minimum of f along the
+// edge (again a weighted median) and let the kink reached join the vertex.
+// Returns the status; u (lane q) and c (lane j) hold the last dual values.
+template <int R>
+LADL_INL int finisher(Wave<R> &w, float (&rv)[R], uint32_t &zbits, int &s, float &f, float &u, float &c,
+                      bool &unique, int maxp)
+{
+    constexpr int LDN = Wave<R>::LDN;
+    const int l = lane_id(), p = w.p;
+    const float lam = w.lam;
+    for (int it = 0;; ++it) {
+        if (!vertex_eval<R>(w, rv, zbits, s, f)) return ST_NOTCERT;
+        if (certificate<R>(w, rv, zbits, s, u, c, unique)) return unique ? ST_CERTIFIED : ST_NONUNIQUE;
+        if (it >= maxp) return ST_MAXITER;
+        uint32_t smask = 0;
+        for (int q = 0; q < s; ++q) smask |= 1u << uni(w.ss[q]);
+        const bool offS = (l < p) && !((smask >> l) & 1u);
+        const float colabs = (l < p) ? w.vca[l] : 0.f;
+        float vr = (l < s && 1.f - fabsf(u) < -TOL_U) ? 1.f - fabsf(u) : FINF;
+        float vcl = (offS && fabsf(c) > lam * (1.f + TOL_C) + TOL_CA * colabs) ? lam - fabsf(c) : FINF;
+        float m = wmin(fminf(vr, vcl));
+        if (m == FINF) return ST_NOTCERT;
+        uint64_t rbal = ballot(vr == m);
+        const bool type1 = rbal != 0;
+        const int sel = type1 ? first_lane(rbal) : first_lane(ballot(vcl == m));
+        float rhs = 0.f, dj0 = 0.f, usel = 0.f;
+        if (type1) {
+            usel = rdlane(u, sel);
+            rhs = (l == sel) ? -sgnf(usel) : 0.f;
+        } else {
+            dj0 = sgnf(rdlane(c, sel));
+            rhs = (l < s) ? -w.Xs[sel * LDN + w.zs[l]] * dj0 : 0.f;
+        }
+        const float dS = lu_solve(w.A, w.piv, s, rhs);
+        if (l < p) w.vd[l] = 0.f;
+        __syncthreads();
+        if (l < s) w.vd[w.ss[l]] = dS;
+        if (!type1 && l == 0) w.vd[sel] = dj0;
+        __syncthreads();
+        float xd[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) xd[k] = 0.f;
+        for (int q = 0; q < s; ++q) {
+            int jc = uni(w.ss[q]);
+            float dc = rdlane(dS, q);
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                if (k < w.nslot) xd[k] = fmaf(w.Xs[jc * LDN + 64 * k + l], dc, xd[k]);
+        }
+        if (!type1) {
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                if (k < w.nslot) xd[k] = fmaf(w.Xs[sel * LDN + 64 * k + l], dj0, xd[k]);
+        }
+        const int zsel = type1 ? uni(w.zs[sel]) : -1;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if ((zbits >> k) & 1u) xd[k] = (64 * k + l == zsel) ? -sgnf(usel) : 0.f;
+        // f(b + t d) = sum |r_i - t xd_i| + lam sum |b_j + t d_j|: kinks at
+        // r_i/xd_i (weight |xd_i|) and -b_j/d_j (weight lam |d_j|)
+        float bel = 0.f, at = 0.f, tot = 0.f;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            float ax = fabsf(xd[k]);
+            bool z = rv[k] == 0.f;
+            bool neg = __builtin_signbit(rv[k]) != __builtin_signbit(xd[k]);
+            tot += ax;
+            at += z ? ax : 0.f;
+            bel += (!z && neg) ? ax : 0.f;
+        }
+        const float dl = (l < p) ? w.vd[l] : 0.f;
+        const float bl = (l < p) ? w.vt[l] : 0.f;
+        {
+            float wvv = lam * fabsf(dl);
+            bool z = bl == 0.f;
+            bool neg = __builtin_signbit(bl) == __builtin_signbit(dl); // -b/d < 0
+            tot += wvv;
+            at += z ? wvv : 0.f;
+            bel += (!z && neg) ? wvv : 0.f;
+        }
+        wsum3(bel, at, tot);
+        const float need = 0.5f * tot - bel - at;
+        if (!(need > 0.f)) return ST_NOTCERT;
+        float a[R], wt[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            bool pos = rv[k] != 0.f && xd[k] != 0.f &&
+                       __builtin_signbit(rv[k]) == __builtin_signbit(xd[k]);
+            float ax = fabsf(xd[k]);
+            a[k] = pos ? fabsf(rv[k]) / ax : FINF;
+            wt[k] = pos ? ax : 0.f;
+        }
+        const bool vpos = (l < p) && lam > 0.f && dl != 0.f && bl != 0.f &&
+                          __builtin_signbit(bl) != __builtin_signbit(dl);
+        const float av = vpos ? fabsf(bl) / fabsf(dl) : FINF;
+        const float wv = vpos ? lam * fabsf(dl) : 0.f;
+        Sel sr = wselect<R>(w, a, wt, av, wv, need, false);
+        if (!(sr.a > 0.f) || sr.a == FINF) return ST_NOTCERT;
+        // new vertex
+        if (type1) {
+            if (!sr.virt) {
+                if (l == 0) w.zs[sel] = 64 * sr.slot + sr.lane;
+            } else {
+                if (l == 0) {
+                    int c0 = -1;
+                    for (int q = 0; q < s; ++q)
+                        if (w.ss[q] == sr.lane) c0 = q;
+                    for (int q = c0; q + 1 < s; ++q) w.ss[q] = w.ss[q + 1];
+                    for (int q = sel; q + 1 < s; ++q) w.zs[q] = w.zs[q + 1];
+                }
+                s -= 1;
+            }
+        } else {
+            if (!sr.virt) {
+                if (s >= 32) return ST_NOTCERT;
+                if (l == 0) {
+                    w.zs[s] = 64 * sr.slot + sr.lane;
+                    w.ss[s] = sel;
+                }
+                s += 1;
+            } else {
+                if (sr.lane == sel) return ST_NOTCERT;
+                if (l == 0)
+                    for (int q = 0; q < s; ++q)
+                        if (w.ss[q] == sr.lane) w.ss[q] = sel;
+            }
+        }
+        __syncthreads();
+        zbits = 0;
+        for (int q = 0; q < s; ++q) {
+            int zq = uni(w.zs[q]);
+            if ((zq & 63) == l) zbits |= 1u << (zq >> 6);
+        }
+        w.c_pivots++;
+    }
+    return ST_MAXITER;
+}
+
+// Degenerate vertices (more rows on their hyperplanes than active axes,
+// e.g. duplicated rows) can make the edge steps cycle; a tiny deterministic
+// perturbation of y separates such rows.
+template <int R>
+LADL_INL void perturb_y(Wave<R> &w)
+{
+    const int l = lane_id();
+    const float ybar = w.ynorm1 / (float)w.n;
+    for (int i = l; i < w.n; i += 64) {
+        uint32_t h = (uint32_t)i * 2654435761u;
+        float mag = 0.5f + 0.5f * (float)((h >> 8) & 0xFFFFu) * (1.f / 65535.f);
+        float sg = (h >> 31) ? -1.f : 1.f;
+        w.ys[i] += 1.52587890625e-05f * (fabsf(w.ys[i]) + ybar) * mag * sg; // 2^-16
+    }
+    __syncthreads();
+}
+
+// objective of b (in bvec) recomputed with fp64 residuals and sums
+template <int R>
+LADL_INL float objective64(Wave<R> &w, const float *bvec)
+{
+    constexpr int LDN = Wave<R>::LDN;
+    const int l = lane_id();
+    double acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = (k < w.nslot) ? (double)w.ys[64 * k + l] : 0.0;
+    for (int j = 0; j < w.p; ++j) {
+        double bj = (double)unif(bvec[j]);
+        if (bj != 0.0) {
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                if (k < w.nslot) acc[k] -= (double)w.Xs[j * LDN + 64 * k + l] * bj;
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) s += fabs(acc[k]);
+    s += (l < w.p) ? (double)w.lam * fabs((double)bvec[l]) : 0.0;
+    return (float)wsum_d(s);
+}
+
+// --------------------------------------------------------------------------
+// one solve (all its path steps)
+// --------------------------------------------------------------------------
+template <int R>
+LADL_INL void solve_item(Wave<R> &w, const SolveArgs &a, int s)
+{
+    const int l = lane_id();
+    const int k = a.problem ? a.problem[s] : s;
+    const int64_t r0 = a.row_off[k];
+    w.n = (int)(a.row_off[k + 1] - r0);
+    w.p = a.p_arr[k];
+    w.nslot = (w.n + 63) >> 6;
+    const int p = w.p;
+    const bool finite = load_problem<R>(w, a.X + a.x_off[k], a.y + r0);
+    const int64_t bbase = (int64_t)a.path_len * a.b_off[s];
+    // starting point
+    float b0 = 0.f;
+    if (a.t0 > 0)
+        b0 = (l < p) ? a.b_out[bbase + (int64_t)(a.t0 - 1) * p + l] : 0.f;
+    else if (a.b_init)
+        b0 = (l < p) ? a.b_init[a.b_off[s] + l] : 0.f;
+    if (l < 32) w.vb[l] = (l < p && __builtin_isfinite(b0)) ? b0 : 0.f;
+    __syncthreads();
+    float r[R], rb[R], rv[R];
+    for (int t = a.t0; t < a.t1; ++t) {
+        const int64_t o = (int64_t)s * a.path_len + t;
+        float *bout = a.b_out + bbase + (int64_t)t * p;
+        const float lam_in = a.lam[o];
+        w.c_sweeps = w.c_updates = w.c_probes = w.c_pivots = 0;
+        int status;
+        float fout = 0.f;
+        int zcount = -1; // vertex rows to report (-1: none)
+        if (!finite || !(lam_in >= 0.f)) {
+            status = finite ? ST_BADLAMBDA : ST_NONFINITE;
+            if (l < p) w.vb[l] = 0.f;
+            __syncthreads();
+            fout = __builtin_nanf("");
+        } else {
+            w.lam = fmaxf(lam_in, w.opt.lambda_min);
+            residuals<R>(w, r);
+            float f = objective<R>(w, r, w.vb);
+            status = ST_NOTCERT;
+            bool done = false, unique = false, have_vertex = false;
+            uint32_t zbits = 0;
+            int vs = -1;
+            float u = 0.f, c = 0.f, fv = 0.f;
+            const bool snap = !(w.opt.flags & FLAG_NO_SNAP);
+            const int rounds = (p < 2) ? 0 : ((w.opt.max_rounds < 0) ? p : w.opt.max_rounds);
+            const float B = (w.lam > 0.f) ? w.ynorm1 / w.lam : FINF;
+            Chop q;
+            int phase = 0; // 0: unrestricted CCD done, 1: a chop probe done
+            int frozen = -1, round = 0, kax = 0;
+            float fbest = FINF;
+            for (;;) {
+                f = ccd<R>(w, r, frozen, f); // the only CCD call site
+                float sprobe = 0.f;
+                bool more;
+                if (phase == 0) {
+                    if (snap) {
+                        vs = choose_vertex<R>(w, r, zbits);
+                        have_vertex = vs >= 0;
+                        if (have_vertex) {
+                            int st = finisher<R>(w, rv, zbits, vs, fv, u, c, unique, 0);
+                            if (st == ST_CERTIFIED || st == ST_NONUNIQUE) {
+                                status = st;
+                                done = true;
+                                break;
+                            }
+                        }
+                    }
+                    if (round >= rounds) break;
+                    if (round == 0) {
+                        float bl = (l < p) ? fabsf(w.vb[l]) : -1.f;
+                        float bm = wmax(bl);
+                        kax = first_lane(ballot(l < p && bl == bm));
+                    } else {
+                        kax = (kax + 1) % p;
+                    }
+                    ++round;
+                    if (l < p) w.vbb[l] = w.vb[l];
+#pragma unroll
+                    for (int kk = 0; kk < R; ++kk) rb[kk] = r[kk];
+                    fbest = f;
+                    __syncthreads();
+                    chop_init(q, unif(w.vbb[kax]), f, B);
+                    more = chop_next(q, 0.f, sprobe, w.opt);
+                } else {
+                    w.c_probes++;
+                    if (f < fbest) {
+                        fbest = f;
+                        if (l < p) w.vbb[l] = w.vb[l];
+#pragma unroll
+                        for (int kk = 0; kk < R; ++kk) rb[kk] = r[kk];
+                        __syncthreads();
+                    }
+                    more = chop_next(q, f, sprobe, w.opt);
+                }
+                // next CCD starts from the best point; a probe sets b_kax := s
+                if (l < p) w.vb[l] = w.vbb[l];
+#pragma unroll
+                for (int kk = 0; kk < R; ++kk) r[kk] = rb[kk];
+                __syncthreads();
+                if (more) {
+                    const float d = sprobe - unif(w.vbb[kax]);
+                    if (d != 0.f) {
+                        constexpr int LDN = Wave<R>::LDN;
+#pragma unroll
+                        for (int kk = 0; kk < R; ++kk)
+                            if (kk < w.nslot) r[kk] = fmaf(-w.Xs[kax * LDN + 64 * kk + l], d, r[kk]);
+                    }
+                    if (l == 0) w.vb[kax] = sprobe;
+                    __syncthreads();
+                    f = objective<R>(w, r, w.vb);
+                    frozen = kax;
+                    phase = 1;
+                } else {
+                    f = fbest;
+                    frozen = -1;
+                    phase = 0;
+                }
+            }
+            if (!done && snap && have_vertex && !(w.opt.flags & FLAG_NO_FINISHER)) {
+                const int maxp = (w.opt.max_pivots > 0) ? w.opt.max_pivots : 4 * p + 32;
+                bool perturbed = false;
+                for (int attempt = 0; attempt < 2 && !done; ++attempt) {
+                    if (attempt == 1) {
+                        perturb_y<R>(w);
+                        perturbed = true;
+                    }
+                    status = finisher<R>(w, rv, zbits, vs, fv, u, c, unique, maxp);
+                    done = (status == ST_CERTIFIED || status == ST_NONUNIQUE);
+                }
+                if (done && perturbed) {
+                    // The perturbed problem's dual vector (u_i = sign r_i off Z,
+                    // u_Z) is feasible for the original problem, whose
+                    // optimum is therefore >= y.u.  Take the same vertex with
+                    // the original y and accept it if f - y.u is tiny.
+                    float sg[R];
+#pragma unroll
+                    for (int kk = 0; kk < R; ++kk) sg[kk] = sgnf(rv[kk]);
+                    const float *yg = a.y + r0;
+                    for (int i = l; i < w.n; i += 64) w.ys[i] = yg[i];
+                    __syncthreads();
+                    double yu = 0.0;
+#pragma unroll
+                    for (int kk = 0; kk < R; ++kk)
+                        if (kk < w.nslot) yu += (double)w.ys[64 * kk + l] * (double)sg[kk];
+                    if (l < vs) yu += (double)w.ys[w.zs[l]] * (double)u;
+                    yu = wsum_d(yu);
+                    done = vertex_eval<R>(w, rv, zbits, vs, fv);
+                    if (done) {
+                        float fo = objective64<R>(w, w.vt);
+                        done = (double)fo - yu <= 2e-6 * fmax(1.0, (double)fo);
+                    }
+                    status = done ? ST_NONUNIQUE : ST_NOTCERT;
+                }
+            }
+            if (done) {
+                if (l < p) w.vb[l] = w.vt[l];
+                zcount = vs;
+                __syncthreads();
+            } else if (!snap) {
+                status = ST_MAXITER;
+            }
+            fout = objective64<R>(w, w.vb);
+        }
+        // outputs
+        if (l < p) bout[l] = w.vb[l];
+        uint64_t act = ballot(l < p && w.vb[l] != 0.f);
+        if (l == 0) {
+            a.obj_out[o] = fout;
+            a.active_out[o] = (uint32_t)act;
+            a.status_out[o] = status;
+            if (a.iters_out) {
+                a.iters_out[4 * o + 0] = w.c_sweeps;
+                a.iters_out[4 * o + 1] = w.c_updates;
+                a.iters_out[4 * o + 2] = w.c_probes;
+                a.iters_out[4 * o + 3] = w.c_pivots;
+            }
+        }
+        if (l < 32) {
+            int val = -1;
+            if (zcount > 0 && l < zcount) {
+                int zl = w.zs[l], rank = 0;
+                for (int q = 0; q < zcount; ++q) rank += (uni(w.zs[q]) < zl) ? 1 : 0;
+                a.zrows_out[(int64_t)ZPAD * o + rank] = zl;
+            } else {
+                a.zrows_out[(int64_t)ZPAD * o + l] = val;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(64) void k_wave(SolveArgs a)
+{
+    extern __shared__ float smem[];
+    Wave<R> w;
+    carve<R>(w, smem, a.pmax);
+    w.opt = a.opt;
+    const int l = lane_id();
+    for (;;) {
+        int q = 0;
+        if (l == 0) q = atomicAdd(a.counter, 1);
+        q = rdlane(q, 0);
+        if (q >= a.num_items) break;
+        solve_item<R>(w, a, a.order[q]);
+    }
+}
+
+__global__ void k_reset(int32_t *c, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = 0;
+}
+
+size_t wave_lds_bytes(int R, int pmax) { return 4 * wave_lds_floats(R, pmax); }
+
+hipError_t launch_reset(int32_t *counters, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset, dim3((n + 63) / 64), dim3(64), 0, s, counters, n);
+    return hipGetLastError();
+}
+
+template <int R>
+static hipError_t launch_wave_t(const SolveArgs &a, int grid, hipStream_t s)
+{
+    size_t lds = wave_lds_bytes(R, a.pmax);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_wave<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_wave<R>, dim3(grid), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int R>
+static int max_blocks_t(int pmax)
+{
+    int nb = 0;
+    size_t lds = wave_lds_bytes(R, pmax);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_wave<R>, 64, lds) != hipSuccess) return 0;
+    return nb;
+}
+
+hipError_t launch_wave(int R, const SolveArgs &a, int grid, hipStream_t s)
+{
+    switch (R) {
+    case 1: return launch_wave_t<1>(a, grid, s);
+    case 2: return launch_wave_t<2>(a, grid, s);
+    case 4: return launch_wave_t<4>(a, grid, s);
+    case 8: return launch_wave_t<8>(a, grid, s);
+    case 16: return launch_wave_t<16>(a, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int wave_max_blocks_per_cu(int R, int pmax)
+{
+    switch (R) {
+    case 1: return max_blocks_t<1>(pmax);
+    case 2: return max_blocks_t<2>(pmax);
+    case 4: return max_blocks_t<4>(pmax);
+    case 8: return max_blocks_t<8>(pmax);
+    case 16: return max_blocks_t<16>(pmax);
+    default: return 0;
+    }
+}
+
+} // namespace ladl

@@ -1,0 +1,167 @@
+// Wavefront primitives for gfx950 (wave64): DPP reductions and scans,
+// ballot/mbcnt compaction helpers and a 64-lane bitonic sort.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ladl {
+
+constexpr int WAVE = 64;
+constexpr float FINF = __builtin_inff();
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ int fbits(float v) { return __builtin_bit_cast(int, v); }
+__device__ __forceinline__ float bitsf(int v) { return __builtin_bit_cast(float, v); }
+
+// lane `l` of v; l must be wave-uniform
+__device__ __forceinline__ float rdlane(float v, int l) { return bitsf(__builtin_amdgcn_readlane(fbits(v), l)); }
+__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// DPP move: lanes whose source is outside the row, or whose row/bank is
+// masked off, receive `old`.
+template <int CTRL, int ROWM = 0xF, int BANKM = 0xF>
+__device__ __forceinline__ float dpp(float old, float v)
+{
+    return bitsf(__builtin_amdgcn_update_dpp(fbits(old), fbits(v), CTRL, ROWM, BANKM, false));
+}
+template <int CTRL, int ROWM = 0xF, int BANKM = 0xF>
+__device__ __forceinline__ int dppi(int old, int v)
+{
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWM, BANKM, false);
+}
+
+// DPP controls (GFX9 encoding)
+constexpr int DPP_XOR1 = 0xB1;    // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;    // quad_perm [2,3,0,1]
+constexpr int DPP_HMIRROR = 0x141; // row_half_mirror
+constexpr int DPP_MIRROR = 0x140;  // row_mirror
+constexpr int DPP_SHR1 = 0x111, DPP_SHR2 = 0x112, DPP_SHR4 = 0x114, DPP_SHR8 = 0x118;
+constexpr int DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
+
+// Butterfly within each row of 16 lanes, then the four row results
+// combined through readlane: every lane returns the same value, and the
+// order of the additions is fixed.
+__device__ __forceinline__ float wsum(float v)
+{
+    v += dpp<DPP_XOR1>(0.f, v);
+    v += dpp<DPP_XOR2>(0.f, v);
+    v += dpp<DPP_HMIRROR>(0.f, v);
+    v += dpp<DPP_MIRROR>(0.f, v);
+    return (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
+}
+
+// three independent sums, interleaved for latency
+__device__ __forceinline__ void wsum3(float &a, float &b, float &c)
+{
+    a += dpp<DPP_XOR1>(0.f, a);
+    b += dpp<DPP_XOR1>(0.f, b);
+    c += dpp<DPP_XOR1>(0.f, c);
+    a += dpp<DPP_XOR2>(0.f, a);
+    b += dpp<DPP_XOR2>(0.f, b);
+    c += dpp<DPP_XOR2>(0.f, c);
+    a += dpp<DPP_HMIRROR>(0.f, a);
+    b += dpp<DPP_HMIRROR>(0.f, b);
+    c += dpp<DPP_HMIRROR>(0.f, c);
+    a += dpp<DPP_MIRROR>(0.f, a);
+    b += dpp<DPP_MIRROR>(0.f, b);
+    c += dpp<DPP_MIRROR>(0.f, c);
+    a = (rdlane(a, 0) + rdlane(a, 16)) + (rdlane(a, 32) + rdlane(a, 48));
+    b = (rdlane(b, 0) + rdlane(b, 16)) + (rdlane(b, 32) + rdlane(b, 48));
+    c = (rdlane(c, 0) + rdlane(c, 16)) + (rdlane(c, 32) + rdlane(c, 48));
+}
+
+__device__ __forceinline__ float wmin(float v)
+{
+    v = fminf(v, dpp<DPP_XOR1>(v, v));
+    v = fminf(v, dpp<DPP_XOR2>(v, v));
+    v = fminf(v, dpp<DPP_HMIRROR>(v, v));
+    v = fminf(v, dpp<DPP_MIRROR>(v, v));
+    return fminf(fminf(rdlane(v, 0), rdlane(v, 16)), fminf(rdlane(v, 32), rdlane(v, 48)));
+}
+
+__device__ __forceinline__ float wmax(float v)
+{
+    v = fmaxf(v, dpp<DPP_XOR1>(v, v));
+    v = fmaxf(v, dpp<DPP_XOR2>(v, v));
+    v = fmaxf(v, dpp<DPP_HMIRROR>(v, v));
+    v = fmaxf(v, dpp<DPP_MIRROR>(v, v));
+    return fmaxf(fmaxf(rdlane(v, 0), rdlane(v, 16)), fmaxf(rdlane(v, 32), rdlane(v, 48)));
+}
+
+__device__ __forceinline__ int wmin_i(int v)
+{
+    v = min(v, dppi<DPP_XOR1>(v, v));
+    v = min(v, dppi<DPP_XOR2>(v, v));
+    v = min(v, dppi<DPP_HMIRROR>(v, v));
+    v = min(v, dppi<DPP_MIRROR>(v, v));
+    return min(min(rdlane(v, 0), rdlane(v, 16)), min(rdlane(v, 32), rdlane(v, 48)));
+}
+
+// double-precision sum (used only by the optimality certificate)
+__device__ __forceinline__ double wsum_d(double v)
+{
+    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// inclusive prefix sum across the 64 lanes (row shifts, then row
+// broadcasts of lanes 15 and 31)
+__device__ __forceinline__ float wscan_incl(float v)
+{
+    v += dpp<DPP_SHR1>(0.f, v);
+    v += dpp<DPP_SHR2>(0.f, v);
+    v += dpp<DPP_SHR4>(0.f, v);
+    v += dpp<DPP_SHR8>(0.f, v);
+    v += dpp<DPP_BCAST15, 0xA>(0.f, v);
+    v += dpp<DPP_BCAST31, 0xC>(0.f, v);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
+__device__ __forceinline__ int first_lane(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
+// number of set bits of m in lanes below this one
+__device__ __forceinline__ int mbcnt(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// ascending sort of (key, val) pairs held one per lane
+__device__ __forceinline__ void bitonic64(float &key, float &val)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            float ok = __shfl_xor(key, j);
+            float ov = __shfl_xor(val, j);
+            bool asc = (l & k) == 0;
+            bool lower = (l & j) == 0;
+            bool take = (asc == lower) ? (ok < key) : (ok > key);
+            key = take ? ok : key;
+            val = take ? ov : val;
+        }
+    }
+}
+
+__device__ __forceinline__ void bitonic64(float &key)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            float ok = __shfl_xor(key, j);
+            bool asc = (l & k) == 0;
+            bool lower = (l & j) == 0;
+            bool take = (asc == lower) ? (ok < key) : (ok > key);
+            key = take ? ok : key;
+        }
+    }
+}
+
+__device__ __forceinline__ float sgnf(float v) { return (v > 0.f) ? 1.f : ((v < 0.f) ? -1.f : 0.f); }
+
+} // namespace ladl

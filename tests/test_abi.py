@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every function include/ladlasso.h
+declares (no GPU needed: nothing is computed)."""
+import ctypes
+import os
+import re
+
+import paper_2510_15649_amd as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "ladlasso.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ladl_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    lib = ctypes.CDLL(L.LIB_PATH)
+    names = header_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(L.EXPORTED)
+
+
+def test_host_only_entry_points():
+    lib = L.lib()
+    o = L.default_options()
+    assert o.max_sweeps == 64 and o.max_rounds == 1 and o.schedule == -1
+    assert abs(o.tol_s - 2 ** -20) < 1e-12
+    assert lib.ladl_error_string(L.EINVAL).startswith(b"LADL_EINVAL")
+    assert lib.ladl_error_string(L.OK) == b"LADL_OK"
+    # NULL arguments are rejected before any device work
+    assert lib.ladl_create(None) == L.EINVAL
+    assert lib.ladl_plan_create(None, None, None, None) == L.EINVAL
+    assert lib.ladl_solve_f32(*([None] * 12)) == L.EINVAL
+    assert b"NULL" in lib.ladl_last_error_detail()
+
+
+def test_no_packed_fp32_or_scalar_stores_in_device_code():
+    """Device code is built without packed fp32 instructions and without
+    stores through the scalar data cache (checked on the assembly hipcc
+    emits for the kernels of this repository)."""
+    import subprocess
+    import tempfile
+    src = os.path.join(ROOT, "paper_2510_15649_amd", "csrc", "ladl_solve_wave.hip")
+    with tempfile.TemporaryDirectory() as td:
+        out = os.path.join(td, "k.s")
+        subprocess.check_call(["/opt/rocm/bin/hipcc", "-O3", "-std=c++17", "--offload-arch=gfx950", "-x", "hip",
+                               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only",
+                               "-S", src, "-I", os.path.join(ROOT, "include"), "-o", out],
+                              stderr=subprocess.DEVNULL)
+        asm = open(out).read()
+    assert "v_pk_fma_f32" not in asm and "v_pk_add_f32" not in asm and "v_pk_mul_f32" not in asm
+    assert not re.search(r"\bs_(store|atomic|buffer_store|dcache_wb)", asm)

@@ -321,3 +321,22 @@ def test_backward_matches_finite_differences():
             assert abs(fd - an) <= 1e-6 * (1 + abs(an)), (kind, i, j, fd, an)
             checked += 1
     assert checked > 50
+
+
+def test_duplicated_rows_degenerate_vertex():
+    """Duplicated rows put more rows on their hyperplanes than there are
+    active axes (a degenerate vertex of the Section 3.1 LP); the oracle still
+    reaches and certifies the optimum (checked against HiGHS)."""
+    rng = np.random.default_rng(13)
+    for _ in range(60):
+        n0, p = int(rng.integers(3, 30)), int(rng.integers(1, 6))
+        X = rng.standard_normal((n0, p))
+        y = rng.standard_normal(n0) * 2
+        reps = rng.integers(1, 4, size=n0)
+        Xd, yd = np.repeat(X, reps, axis=0), np.repeat(y, reps)
+        lam = float(10 ** rng.uniform(-2, 1))
+        fh, _ = lp_highs(Xd, yd, lam)
+        for rounds in (0, 1):
+            b, info = O.solve(Xd, yd, lam, max_rounds=rounds)
+            assert info["certified"]
+            assert abs(f_np(Xd, yd, lam, b) - fh) <= 1e-9 * max(1, fh)
