@@ -581,12 +581,17 @@ LADL_INL bool chop_next(Chop &q, float F, float &s, const DevOpt &opt)
 // H7: vertices, LU in LDS, certificate, finisher
 // --------------------------------------------------------------------------
 
-// the p hyperplanes ({x_i.b = y_i} or {b_j = 0}) nearest to the point
-// (vb, r): rows |r_i|/||x_i||, axes |b_j|; ties: axes first, then lower row.
-// Writes zs/ss and the per-lane Z bits; returns |S| (= |Z|) or -1.
+// The vertex nearest to the point (vb, r): of the hyperplanes
+// {x_i.b = y_i} and {b_j = 0}, take p that meet in one point, nearest first
+// (rows |r_i|/||x_i||, axes |b_j|; ties: axes first, then lower row).  A
+// hyperplane whose normal depends linearly on those already taken (a
+// duplicated row, say) is passed over (modified Gram-Schmidt, basis kept in
+// the A area of LDS).  Writes zs/ss and the per-lane Z bits; returns |S|
+// (= |Z|) or -1.
 template <int R>
 LADL_INL int choose_vertex(Wave<R> &w, const float (&r)[R], uint32_t &zbits)
 {
+    constexpr int LDN = Wave<R>::LDN;
     const int l = lane_id(), p = w.p;
     float dist[R];
 #pragma unroll
@@ -595,35 +600,57 @@ LADL_INL int choose_vertex(Wave<R> &w, const float (&r)[R], uint32_t &zbits)
         dist[k] = (nr > 0.f) ? fabsf(r[k]) / nr : FINF;
     }
     const float dv = (l < p) ? fabsf(w.vb[l]) : FINF;
+    float *Q = w.A;
     zbits = 0;
-    bool ctaken = false;
-    int nz = 0;
-    for (int q = 0; q < p; ++q) {
+    uint32_t seen = 0;
+    bool cseen = false, ctaken = false;
+    int acc = 0, nz = 0;
+    for (int guard = 0; guard < w.n + p && acc < p; ++guard) {
         float mr = FINF;
 #pragma unroll
         for (int k = 0; k < R; ++k)
-            if (!((zbits >> k) & 1u)) mr = fminf(mr, dist[k]);
-        float m = wmin(fminf(mr, ctaken ? FINF : dv));
-        if (m == FINF) return -1;
-        uint64_t cb = ballot(!ctaken && l < p && dv == m);
+            if (!((seen >> k) & 1u)) mr = fminf(mr, dist[k]);
+        const float m = wmin(fminf(mr, cseen ? FINF : dv));
+        if (m == FINF) break;
+        const uint64_t cb = ballot(!cseen && l < p && dv == m);
+        int row = -1, col = -1;
         if (cb) {
-            if (l == first_lane(cb)) ctaken = true;
+            col = first_lane(cb);
+            if (l == col) cseen = true;
         } else {
             int best = INT_MAX;
 #pragma unroll
             for (int k = R - 1; k >= 0; --k)
-                if (!((zbits >> k) & 1u) && dist[k] == m) best = 64 * k + l;
-            int gi = wmin_i(best);
-            if (l == (gi & 63)) zbits |= 1u << (gi >> 6);
-            if (l == 0) w.zs[nz] = gi;
+                if (!((seen >> k) & 1u) && dist[k] == m) best = 64 * k + l;
+            row = wmin_i(best);
+            if (l == (row & 63)) seen |= 1u << (row >> 6);
+        }
+        float v = 0.f;
+        if (l < p) v = (col >= 0) ? ((l == col) ? 1.f : 0.f) : w.Xs[l * LDN + row];
+        const float n0 = sqrtf(wsum(v * v));
+        for (int a2 = 0; a2 < acc; ++a2) {
+            const float qa = (l < p) ? Q[a2 * ALD + l] : 0.f;
+            const float dd = wsum(v * qa);
+            v = fmaf(-dd, qa, v);
+        }
+        const float nv = sqrtf(wsum(v * v));
+        if (!(nv > 1e-4f * n0)) continue; // dependent on the normals taken
+        if (l < p) Q[acc * ALD + l] = v / nv;
+        __syncthreads();
+        ++acc;
+        if (col >= 0) {
+            if (l == col) ctaken = true;
+        } else {
+            if (l == (row & 63)) zbits |= 1u << (row >> 6);
+            if (l == 0) w.zs[nz] = row;
             ++nz;
         }
     }
-    uint64_t sb = ballot(l < p && !ctaken);
-    int s = popc64(sb);
+    const uint64_t sb = ballot(l < p && !ctaken);
+    const int s = popc64(sb);
     if (l < p && !ctaken) w.ss[mbcnt(sb)] = l;
     __syncthreads();
-    return (s == nz) ? s : -1;
+    return (acc == p && s == nz) ? s : -1;
 }
 
 LADL_INL bool lu_factor(float *A, int *piv, int s)
