@@ -405,7 +405,27 @@ int ladl_solve_plain_f32(ladl_plan_t pl, const float *X, const float *y, const f
 {
     int rc = check_solve_ptrs(pl, X, y, lam, b, obj, active, zr, st);
     if (rc) return rc;
-    return fail(LADL_EUNSUPPORTED, "plain kernel not built yet");
+    hipStream_t s = (hipStream_t)stream;
+    // one thread per solve, up to 2^17 threads fetching from the queue
+    const int64_t T = std::min<int64_t>(((int64_t)pl->S + 63) / 64 * 64, 131072);
+    if (!pl->d_gws || pl->gws_stride != T) {
+        (void)hipFree(pl->d_gws);
+        pl->d_gws = nullptr;
+        hipError_t e = hipMalloc((void **)&pl->d_gws, sizeof(float) * (size_t)plain_scratch_floats(pl->nmax, T));
+        if (e != hipSuccess) return hipfail(e, "plain kernel scratch");
+        pl->gws_stride = T;
+    }
+    hipError_t e = launch_reset(pl->d_counter_plain, 1, s);
+    if (e != hipSuccess) return hipfail(e, "queue reset launch");
+    SolveArgs a = base_args(pl, X, y, lam, b_init, b, obj, active, zr, st, it, 0, pl->L);
+    a.order = pl->d_order_plain;
+    a.num_items = pl->S;
+    a.counter = pl->d_counter_plain;
+    a.gws = pl->d_gws;
+    a.gws_stride = T;
+    e = launch_plain(a, pl->nmax, T, s);
+    if (e != hipSuccess) return hipfail(e, "plain kernel launch");
+    return LADL_OK;
 }
 
 int ladl_backward_f32(ladl_plan_t pl, const float *X, const float *b, const int32_t *zr, const int32_t *st,

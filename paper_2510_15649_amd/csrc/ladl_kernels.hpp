@@ -47,7 +47,8 @@ size_t wave_lds_bytes(int R, int pmax);
 int wave_max_blocks_per_cu(int R, int pmax);
 hipError_t launch_reset(int32_t *counters, int n, hipStream_t s);
 hipError_t launch_wave(int R, const SolveArgs &a, int grid, hipStream_t s);
-hipError_t launch_plain(const SolveArgs &a, int grid, int block, hipStream_t s);
+hipError_t launch_plain(const SolveArgs &a, int NM, int64_t nthreads, hipStream_t s);
+int64_t plain_scratch_floats(int NM, int64_t nthreads);
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);
 
 } // namespace ladl

@@ -20,26 +20,13 @@
 //   A   vertex matrix / LU factors, 32 x 33
 //   small vectors of 32 (b, best b, column |x| sums, direction, scratch)
 //   gd  32 doubles (certificate), sa/sw 64+64 (selection compaction)
+#include "ladl_common.hpp"
 #include "ladl_kernels.hpp"
 #include "ladl_wave.hpp"
 
 #include <climits>
 
 namespace ladl {
-
-constexpr int FLAG_GOLDEN = 1, FLAG_NO_FINISHER = 2, FLAG_NO_SNAP = 4;
-enum { ST_CERTIFIED = 0, ST_NONUNIQUE = 1, ST_MAXITER = 2, ST_NONFINITE = 3, ST_BADLAMBDA = 4, ST_NOTCERT = 5 };
-
-// optimality certificate slack in fp32 (dual variables computed with fp64 sums)
-constexpr float TOL_U = 1e-4f;   // |u_i| <= 1 + TOL_U on Z
-constexpr float TOL_C = 1e-4f;   // |c_j| <= lambda (1 + TOL_C) + TOL_CA * sum_i |x_ij| off S
-constexpr float TOL_CA = 1e-5f;
-// margins below which a certified vertex is reported as possibly non-unique
-constexpr float MARGIN_U = 1e-3f, MARGIN_C = 1e-3f, MARGIN_R = 1e-5f;
-
-constexpr int ALD = 33; // leading dimension of the vertex matrix
-
-#define LADL_INL __device__ __attribute__((always_inline)) inline
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ float unif(float v) { return bitsf(__builtin_amdgcn_readfirstlane(fbits(v))); }
@@ -452,132 +439,6 @@ LADL_INL float ccd(Wave<R> &w, float (&r)[R], int frozen, float f)
 }
 
 // --------------------------------------------------------------------------
-// H6: ternary chop along axis kax (Sections 3.5-3.6), as a state machine fed
-// with one probe value F(s) at a time so that the solve has a single CCD
-// call site.  F(s) = f after CCD with b_kax := s and axis kax frozen,
-// started from the best point found so far.  The range c +- max(1,|c|) is
-// extended by doubling while an end is lower than the centre (clamped to
-// |b_kax| <= ||y||_1 / lambda, which bounds every minimiser), then cut in
-// thirds (or golden sections) keeping the better side.
-// --------------------------------------------------------------------------
-struct Chop {
-    float lo, hi, c, h, B, Fc, Flo, Fhi, m1, m2, F1, F2;
-    int stage, which, ext, it;
-    bool have1, have2;
-};
-
-LADL_INL void chop_init(Chop &q, float c, float f, float B)
-{
-    q.B = B;
-    q.c = c;
-    q.h = fmaxf(1.f, fabsf(c));
-    q.lo = fmaxf(c - q.h, -B);
-    q.hi = fminf(c + q.h, B);
-    q.Fc = f;
-    q.Flo = q.Fhi = q.F1 = q.F2 = FINF;
-    q.m1 = q.m2 = 0.f;
-    q.stage = 0;
-    q.which = 0;
-    q.ext = 0;
-    q.it = 0;
-    q.have1 = q.have2 = false;
-}
-
-// Record the value of the last requested probe (when which != 0) and return
-// the next probe point in s; false when the chop is finished.
-LADL_INL bool chop_next(Chop &q, float F, float &s, const DevOpt &opt)
-{
-    switch (q.which) {
-    case 1: q.Flo = F; break;
-    case 2: q.Fhi = F; break;
-    case 3: q.F1 = F; q.have1 = true; break;
-    case 4: q.F2 = F; q.have2 = true; break;
-    default: break;
-    }
-    const bool golden = (opt.flags & FLAG_GOLDEN) != 0;
-    const float g = 0.381966011f;
-    for (int guard = 0; guard < 8; ++guard) {
-        switch (q.stage) {
-        case 0: // F(lo)
-            q.stage = 1;
-            q.which = 1;
-            s = q.lo;
-            return true;
-        case 1: // F(hi)
-            q.stage = 2;
-            q.which = 2;
-            s = q.hi;
-            return true;
-        case 2: // extend to the left while F(lo) < F(c)
-            if (q.Flo < q.Fc && q.lo > -q.B && q.ext < 64) {
-                q.hi = q.c;
-                q.Fhi = q.Fc;
-                q.c = q.lo;
-                q.Fc = q.Flo;
-                q.h *= 2.f;
-                q.lo = fmaxf(q.c - q.h, -q.B);
-                ++q.ext;
-                q.which = 1;
-                s = q.lo;
-                return true;
-            }
-            q.stage = 3;
-            break;
-        case 3: // extend to the right while F(hi) < F(c)
-            if (q.Fhi < q.Fc && q.hi < q.B && q.ext < 128) {
-                q.lo = q.c;
-                q.Flo = q.Fc;
-                q.c = q.hi;
-                q.Fc = q.Fhi;
-                q.h *= 2.f;
-                q.hi = fminf(q.c + q.h, q.B);
-                ++q.ext;
-                q.which = 2;
-                s = q.hi;
-                return true;
-            }
-            q.stage = 4;
-            break;
-        default: // chop
-            if (q.have1 && q.have2) {
-                if (q.F1 < q.F2) {
-                    q.hi = q.m2;
-                    if (golden) {
-                        q.m2 = q.m1;
-                        q.F2 = q.F1;
-                        q.have1 = false;
-                    } else {
-                        q.have1 = q.have2 = false;
-                    }
-                } else {
-                    q.lo = q.m1;
-                    if (golden) {
-                        q.m1 = q.m2;
-                        q.F1 = q.F2;
-                        q.have2 = false;
-                    } else {
-                        q.have1 = q.have2 = false;
-                    }
-                }
-                ++q.it;
-            }
-            if (q.hi - q.lo <= opt.tol_s * (1.f + fabsf(q.lo) + fabsf(q.hi)) || q.it >= opt.max_ternary) return false;
-            if (!q.have1) {
-                q.m1 = golden ? q.lo + g * (q.hi - q.lo) : q.lo + (q.hi - q.lo) / 3.f;
-                q.which = 3;
-                s = q.m1;
-            } else {
-                q.m2 = golden ? q.hi - g * (q.hi - q.lo) : q.hi - (q.hi - q.lo) / 3.f;
-                q.which = 4;
-                s = q.m2;
-            }
-            return true;
-        }
-    }
-    return false;
-}
-
-// --------------------------------------------------------------------------
 // H7: vertices, LU in LDS, certificate, finisher
 // --------------------------------------------------------------------------
 
@@ -975,12 +836,7 @@ LADL_INL void perturb_y(Wave<R> &w)
 {
     const int l = lane_id();
     const float ybar = w.ynorm1 / (float)w.n;
-    for (int i = l; i < w.n; i += 64) {
-        uint32_t h = (uint32_t)i * 2654435761u;
-        float mag = 0.5f + 0.5f * (float)((h >> 8) & 0xFFFFu) * (1.f / 65535.f);
-        float sg = (h >> 31) ? -1.f : 1.f;
-        w.ys[i] += 1.52587890625e-05f * (fabsf(w.ys[i]) + ybar) * mag * sg; // 2^-16
-    }
+    for (int i = l; i < w.n; i += 64) w.ys[i] += PERTURB_REL * (fabsf(w.ys[i]) + ybar) * perturb_dir(i);
     __syncthreads();
 }
 

@@ -10,6 +10,9 @@ from parity import compare, oracle_ref, to_numpy
 pytestmark = pytest.mark.gpu
 
 
+KERNELS = pytest.mark.parametrize("kernel", ["wave", "plain"])
+
+
 @pytest.fixture(scope="module")
 def torch():
     import torch
@@ -34,9 +37,10 @@ def assert_parity(w, gpu, ref, solves=None, min_strict=0.5):
     assert st["strict"] >= min_strict * st["outputs"], st
 
 
-def test_c0_fp32(torch):
+@KERNELS
+def test_c0_fp32(torch, kernel):
     w = W.config0()
-    plan, g = gpu_solve(torch, w)
+    plan, g = gpu_solve(torch, w, plain=(kernel == "plain"))
     ref = oracle_ref(w)
     assert_parity(w, g, ref, min_strict=1.0)
     # brute force on the same fp32 instance (Section 3.2)
@@ -45,21 +49,24 @@ def test_c0_fp32(torch):
     assert abs(g["obj"][0] - fb) <= 1e-5 * fb
 
 
-def test_c1_subset(torch):
+@KERNELS
+def test_c1_subset(torch, kernel):
     w = W.config1(num_problems=48)
-    plan, g = gpu_solve(torch, w)
+    plan, g = gpu_solve(torch, w, plain=(kernel == "plain"))
     assert_parity(w, g, oracle_ref(w))
 
 
-def test_c3_subset(torch):
+@KERNELS
+def test_c3_subset(torch, kernel):
     w = W.config3(num_problems=96)
-    plan, g = gpu_solve(torch, w)
+    plan, g = gpu_solve(torch, w, plain=(kernel == "plain"))
     assert_parity(w, g, oracle_ref(w))
 
 
-def test_c2_subset(torch):
+@KERNELS
+def test_c2_subset(torch, kernel):
     w = W.config2(num_subsets=160)
-    plan, g = gpu_solve(torch, w)
+    plan, g = gpu_solve(torch, w, plain=(kernel == "plain"))
     assert_parity(w, g, oracle_ref(w))
 
 
@@ -77,7 +84,8 @@ def _pack(blocks, lams):
     return pack("edge", blocks, [b[0].shape[1] for b in blocks], np.arange(len(blocks)), lams, 1)
 
 
-def test_edge_shapes(torch):
+@KERNELS
+def test_edge_shapes(torch, kernel):
     rng = np.random.default_rng(3)
     blocks, lams = [], []
     for n in [1, 2, 3, 5, 63, 64, 65, 127, 128, 129, 255, 257, 511, 513, 1000, 1024]:
@@ -87,11 +95,12 @@ def test_edge_shapes(torch):
             blocks.append((X, y))
             lams.append(float(10 ** rng.uniform(-2, 1)))
     w = _pack(blocks, lams)
-    plan, g = gpu_solve(torch, w)
+    plan, g = gpu_solve(torch, w, plain=(kernel == "plain"))
     assert_parity(w, g, oracle_ref(w), min_strict=0.0)
 
 
-def test_degenerate_inputs(torch):
+@KERNELS
+def test_degenerate_inputs(torch, kernel):
     rng = np.random.default_rng(4)
     n, p = 100, 6
     X = rng.standard_normal((n, p))
@@ -107,7 +116,7 @@ def test_degenerate_inputs(torch):
               (X, y)]                    # lambda = 0: plain LAD
     lmax = float(np.max(np.abs(X.astype(np.float32).astype(np.float64).T @ np.sign(y))))
     w = _pack(blocks, [1.0, 1.0, 0.5, 1.5 * lmax, 0.0])
-    plan, g = gpu_solve(torch, w)
+    plan, g = gpu_solve(torch, w, plain=(kernel == "plain"))
     fails, st = compare(w, g, oracle_ref(w))
     assert not fails, fails
     assert g["obj"][0] == 0.0 and np.all(g["b"][:p] == 0)
@@ -115,14 +124,15 @@ def test_degenerate_inputs(torch):
     assert np.all(g["b"][3 * p: 4 * p] == 0) and g["active"][3] == 0
 
 
-def test_status_codes(torch):
+@KERNELS
+def test_status_codes(torch, kernel):
     rng = np.random.default_rng(5)
     n, p = 80, 4
     blocks = [(rng.standard_normal((n, p)), rng.standard_normal(n)) for _ in range(4)]
     blocks[1][0][7, 2] = np.nan
     blocks[2][1][3] = np.inf
     w = _pack(blocks, [1.0, 1.0, 1.0, -1.0])
-    plan, g = gpu_solve(torch, w)
+    plan, g = gpu_solve(torch, w, plain=(kernel == "plain"))
     assert list(g["status"]) [1:] == [L.NONFINITE, L.NONFINITE, L.BADLAMBDA]
     assert g["status"][0] in (L.CERTIFIED, L.NONUNIQUE)
     fails, _ = compare(w, g, oracle_ref(w, solves=[0]), solves=[0])
