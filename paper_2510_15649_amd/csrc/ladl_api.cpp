@@ -36,7 +36,8 @@ int hipfail(hipError_t e, const char *what)
 }
 
 constexpr int KNOWN_FLAGS = LADL_FLAG_GOLDEN | LADL_FLAG_NO_FINISHER | LADL_FLAG_NO_SNAP;
-constexpr int NMAX_LDS = 1024; // rows per problem held in LDS (16 slots x 64 lanes)
+constexpr int NMAX_ROWS = 2048;     // rows per problem (32 slots x 64 lanes)
+constexpr size_t LDS_RESIDENT_MAX = 40 * 1024; // larger buckets keep X in the global workspace
 
 int rows_per_lane(int n)
 {
@@ -57,6 +58,9 @@ struct Bucket {
     int R = 1, pmax = 1;
     int offset = 0, count = 0; // slice of the order array
     int grid = 0;
+    bool xg = false;           // X in the global workspace instead of LDS
+    int per_cu = 0;
+    int64_t ws_off = 0;        // this bucket's slice of the workspace
 };
 
 struct ladl_plan_s {
@@ -70,8 +74,14 @@ struct ladl_plan_s {
     int64_t *d_row_off = nullptr, *d_x_off = nullptr, *d_b_off = nullptr;
     int32_t *d_p = nullptr, *d_problem = nullptr, *d_order = nullptr, *d_counters = nullptr;
     int32_t *d_order_plain = nullptr, *d_counter_plain = nullptr;
-    float *d_gws = nullptr;
+    float *d_gws = nullptr;      // plain kernel scratch
     int64_t gws_stride = 0;
+    float *d_wws = nullptr;      // wave kernel workspace (buckets with X outside LDS)
+    int64_t wws_floats = 0;
+    // buckets run concurrently on streams forked from the caller's stream
+    std::vector<hipStream_t> bstreams;
+    std::vector<hipEvent_t> ev_join;
+    hipEvent_t ev_fork = nullptr;
     int nmax = 0, pmax = 0;
     bool problems_once = false; // every problem used by exactly one solve
 };
@@ -170,6 +180,13 @@ static void plan_free_device(ladl_plan_s *pl)
     (void)hipFree(pl->d_order_plain);
     (void)hipFree(pl->d_counter_plain);
     (void)hipFree(pl->d_gws);
+    (void)hipFree(pl->d_wws);
+    for (hipStream_t st : pl->bstreams) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : pl->ev_join) (void)hipEventDestroy(ev);
+    if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+    pl->bstreams.clear();
+    pl->ev_join.clear();
+    pl->ev_fork = nullptr;
 }
 
 template <typename T>
@@ -219,7 +236,7 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
     for (int k = 0; k < P; ++k) {
         int64_t n = pl->row_off[k + 1] - pl->row_off[k];
         if (n < 1) return bad(LADL_EINVAL, "problem %d has %lld rows (row_off must increase)", k, (long long)n);
-        if (n > NMAX_LDS) return bad(LADL_EUNSUPPORTED, "problem %d has %lld rows (limit %d)", k, (long long)n, NMAX_LDS);
+        if (n > NMAX_ROWS) return bad(LADL_EUNSUPPORTED, "problem %d has %lld rows (limit %d)", k, (long long)n, NMAX_ROWS);
         int pk = lay->p ? lay->p[k] : lay->p_uniform;
         if (pk < 1 || pk > PMAX) return bad(LADL_EUNSUPPORTED, "problem %d has p = %d (limit 1..%d)", k, pk, PMAX);
         if (!lay->x_off && lay->p && pk != lay->p_uniform)
@@ -253,7 +270,7 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
     }
     pl->b_len = acc * L;
     // buckets by rows per lane; decreasing cost inside a bucket
-    std::vector<int> Rs = {16, 8, 4, 2, 1};
+    std::vector<int> Rs = {32, 16, 8, 4, 2, 1};
     std::vector<int32_t> order;
     order.reserve(S);
     for (int R : Rs) {
@@ -276,13 +293,17 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         for (int s : ids) b.pmax = std::max(b.pmax, (int)pl->p[pl->problem[s]]);
         b.count = (int)ids.size();
         order.insert(order.end(), ids.begin(), ids.end());
-        size_t lds = wave_lds_bytes(R, b.pmax);
+        b.xg = R >= 32 || wave_lds_bytes(R, b.pmax, false) > LDS_RESIDENT_MAX;
+        size_t lds = wave_lds_bytes(R, b.pmax, b.xg);
         if (lds > h->lds_max)
             return bad(LADL_EUNSUPPORTED, "bucket R=%d p=%d needs %zu bytes of LDS (device limit %zu)", R, b.pmax,
                        lds, h->lds_max);
-        int per_cu = wave_max_blocks_per_cu(R, b.pmax);
-        if (per_cu < 1) per_cu = 1;
-        b.grid = std::min<int64_t>(b.count, (int64_t)per_cu * h->num_cu);
+        b.per_cu = std::max(1, wave_max_blocks_per_cu(R, b.pmax, b.xg));
+        b.grid = std::min<int64_t>(b.count, (int64_t)b.per_cu * h->num_cu);
+        if (b.xg) {
+            b.ws_off = pl->wws_floats;
+            pl->wws_floats += (int64_t)b.grid * (int64_t)wave_ws_floats_host(R, b.pmax);
+        }
         pl->buckets.push_back(b);
     }
     // plain kernel: all solves, decreasing cost
@@ -299,10 +320,25 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         (e = upload(&pl->d_problem, pl->problem)) != hipSuccess || (e = upload(&pl->d_order, order)) != hipSuccess ||
         (e = upload(&pl->d_counters, zeros)) != hipSuccess ||
         (e = upload(&pl->d_order_plain, order_plain)) != hipSuccess ||
-        (e = upload(&pl->d_counter_plain, std::vector<int32_t>(1, 0))) != hipSuccess) {
+        (e = upload(&pl->d_counter_plain, std::vector<int32_t>(1, 0))) != hipSuccess ||
+        (pl->wws_floats > 0 && (e = hipMalloc((void **)&pl->d_wws, sizeof(float) * (size_t)pl->wws_floats)) != hipSuccess)) {
         plan_free_device(pl);
         delete pl;
         return hipfail(e, "plan upload");
+    }
+    if (pl->buckets.size() > 1) {
+        pl->bstreams.resize(pl->buckets.size(), nullptr);
+        pl->ev_join.resize(pl->buckets.size(), nullptr);
+        e = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming);
+        for (size_t i = 0; e == hipSuccess && i < pl->buckets.size(); ++i) {
+            e = hipStreamCreateWithFlags(&pl->bstreams[i], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_join[i], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) {
+            plan_free_device(pl);
+            delete pl;
+            return hipfail(e, "plan streams");
+        }
     }
     *out = pl;
     return LADL_OK;
@@ -378,16 +414,27 @@ static int enqueue_wave(ladl_plan_t pl, const float *X, const float *y, const fl
 {
     hipError_t e = launch_reset(pl->d_counters, (int)pl->buckets.size(), s);
     if (e != hipSuccess) return hipfail(e, "queue reset launch");
+    const bool fork = pl->buckets.size() > 1;
+    if (fork && (e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return hipfail(e, "fork event");
     for (size_t bi = 0; bi < pl->buckets.size(); ++bi) {
         const Bucket &bk = pl->buckets[bi];
+        hipStream_t bs = fork ? pl->bstreams[bi] : s;
+        if (fork && (e = hipStreamWaitEvent(bs, pl->ev_fork, 0)) != hipSuccess) return hipfail(e, "fork wait");
         SolveArgs a = base_args(pl, X, y, lam, b_init, b, obj, active, zr, st, it, t0, t1);
         a.order = pl->d_order + bk.offset;
         a.num_items = bk.count;
         a.counter = pl->d_counters + bi;
         a.pmax = bk.pmax;
-        e = launch_wave(bk.R, a, bk.grid, s);
+        if (bk.xg) {
+            a.gws = pl->d_wws + bk.ws_off;
+            a.gws_stride = (int64_t)wave_ws_floats_host(bk.R, bk.pmax);
+        }
+        e = launch_wave(bk.R, bk.xg, a, bk.grid, bs);
         if (e != hipSuccess) return hipfail(e, "solve kernel launch");
+        if (fork && (e = hipEventRecord(pl->ev_join[bi], bs)) != hipSuccess) return hipfail(e, "join event");
     }
+    for (size_t bi = 0; fork && bi < pl->buckets.size(); ++bi)
+        if ((e = hipStreamWaitEvent(s, pl->ev_join[bi], 0)) != hipSuccess) return hipfail(e, "join wait");
     return LADL_OK;
 }
 
@@ -432,7 +479,31 @@ int ladl_backward_f32(ladl_plan_t pl, const float *X, const float *b, const int3
                       int32_t step, const float *grad_b, float *grad_y, float *grad_X, void *stream)
 {
     if (!pl) return fail(LADL_EINVAL, "plan is NULL");
-    return fail(LADL_EUNSUPPORTED, "backward not built yet");
+    if (!X || !b || !zr || !st || !grad_b || !grad_y || !grad_X)
+        return fail(LADL_EINVAL, "a required device pointer is NULL");
+    if (step < 0 || step >= pl->L) return fail(LADL_EINVAL, "step %d outside the path [0, %d)", step, pl->L);
+    if (!pl->problems_once)
+        return fail(LADL_EINVAL, "backward needs every problem used by exactly one solve");
+    BackwardArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.X = X;
+    a.b = b;
+    a.grad_b = grad_b;
+    a.zrows = zr;
+    a.status = st;
+    a.row_off = pl->d_row_off;
+    a.x_off = pl->d_x_off;
+    a.b_off = pl->d_b_off;
+    a.p_arr = pl->d_p;
+    a.problem = pl->d_problem;
+    a.num_solves = pl->S;
+    a.path_len = pl->L;
+    a.step = step;
+    a.grad_y = grad_y;
+    a.grad_X = grad_X;
+    hipError_t e = launch_backward(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hipfail(e, "backward kernel launch");
+    return LADL_OK;
 }
 
 int ladl_graph_create(ladl_plan_t pl, const float *X, const float *y, const float *lam, const float *b_init,
@@ -441,13 +512,45 @@ int ladl_graph_create(ladl_plan_t pl, const float *X, const float *y, const floa
 {
     if (!graph) return fail(LADL_EINVAL, "graph pointer is NULL");
     *graph = nullptr;
-    return fail(LADL_EUNSUPPORTED, "graph path not built yet");
+    int rc = check_solve_ptrs(pl, X, y, lam, b, obj, active, zr, st);
+    if (rc) return rc;
+    auto *g = new (std::nothrow) ladl_graph_s;
+    if (!g) return fail(LADL_ENOMEM, "host allocation");
+    hipError_t e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete g;
+        return hipfail(e, "capture stream");
+    }
+    e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        ladl_graph_destroy(g);
+        return hipfail(e, "begin capture");
+    }
+    // one launch per path step, each warm-started from the previous output
+    for (int t = 0; t < pl->L && rc == LADL_OK; ++t)
+        rc = enqueue_wave(pl, X, y, lam, b_init, b, obj, active, zr, st, it, t, t + 1, g->cap);
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(g->cap, &gr);
+    g->graph = gr;
+    if (rc != LADL_OK || e != hipSuccess) {
+        ladl_graph_destroy(g);
+        return rc != LADL_OK ? rc : hipfail(e, "end capture");
+    }
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        ladl_graph_destroy(g);
+        return hipfail(e, "graph instantiate");
+    }
+    *graph = g;
+    return LADL_OK;
 }
 
 int ladl_graph_launch(ladl_graph_t g, void *stream)
 {
-    if (!g) return fail(LADL_EINVAL, "graph is NULL");
-    return LADL_EUNSUPPORTED;
+    if (!g || !g->exec) return fail(LADL_EINVAL, "graph is NULL");
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hipfail(e, "graph launch");
+    return LADL_OK;
 }
 
 int ladl_graph_destroy(ladl_graph_t g)
@@ -476,8 +579,9 @@ int ladl_plan_describe(ladl_plan_t pl, char *buf, int64_t len)
              pl->L, pl->nmax, pl->pmax, (long long)pl->b_len);
     s += line;
     for (const Bucket &b : pl->buckets) {
-        snprintf(line, sizeof line, "bucket R=%d (n<=%d) pmax=%d solves=%d grid=%d lds=%zuB\n", b.R, 64 * b.R, b.pmax,
-                 b.count, b.grid, wave_lds_bytes(b.R, b.pmax));
+        snprintf(line, sizeof line, "bucket R=%d (n<=%d) pmax=%d solves=%d grid=%d (%d/CU) X in %s lds=%zuB\n", b.R,
+                 64 * b.R, b.pmax, b.count, b.grid, b.per_cu, b.xg ? "HBM workspace" : "LDS",
+                 wave_lds_bytes(b.R, b.pmax, b.xg));
         s += line;
     }
     std::strncpy(buf, s.c_str(), (size_t)len - 1);

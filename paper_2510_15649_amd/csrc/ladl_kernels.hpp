@@ -6,7 +6,7 @@
 namespace ladl {
 
 constexpr int PMAX = 32;     // features per problem
-constexpr int NMAX = 2048;   // rows per problem
+constexpr int NMAX = 2048;   // rows per problem (32 slots x 64 lanes)
 constexpr int ZPAD = 32;     // zero_rows entries per output
 
 struct DevOpt {
@@ -43,10 +43,13 @@ struct BackwardArgs {
 };
 
 // host-side launchers (defined in ladl_kernels.hip)
-size_t wave_lds_bytes(int R, int pmax);
-int wave_max_blocks_per_cu(int R, int pmax);
+// wave kernel: R = row slots per lane (1..32); xg = X held in a per-wave
+// global workspace instead of LDS (required for R = 32)
+size_t wave_lds_bytes(int R, int pmax, bool xg);
+size_t wave_ws_floats_host(int R, int pmax);
+int wave_max_blocks_per_cu(int R, int pmax, bool xg);
 hipError_t launch_reset(int32_t *counters, int n, hipStream_t s);
-hipError_t launch_wave(int R, const SolveArgs &a, int grid, hipStream_t s);
+hipError_t launch_wave(int R, bool xg, const SolveArgs &a, int grid, hipStream_t s);
 hipError_t launch_plain(const SolveArgs &a, int NM, int64_t nthreads, hipStream_t s);
 int64_t plain_scratch_floats(int NM, int64_t nthreads);
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);

@@ -337,15 +337,25 @@ __device__ bool pt_vertex_eval(PT &t, int s, float &f)
     float v[PMAX], e[PMAX];
     for (int q = 0; q < s; ++q) v[q] = t.y[t.zs[q]];
     pt_solve(t, s, v);
-    for (int q = 0; q < s; ++q) {
-        double acc = (double)t.y[t.zs[q]];
-        for (int c = 0; c < s; ++c) acc -= (double)t.x(t.zs[q], t.ss[c]) * (double)v[c];
-        e[q] = (float)acc;
+    // mixed-precision refinement: residual in fp64
+    for (int it = 0; it < 3; ++it) {
+        float cm = 0.f, xm = 0.f;
+        for (int q = 0; q < s; ++q) {
+            double acc = (double)t.y[t.zs[q]];
+            for (int c = 0; c < s; ++c) acc -= (double)t.x(t.zs[q], t.ss[c]) * (double)v[c];
+            e[q] = (float)acc;
+        }
+        pt_solve(t, s, e);
+        for (int q = 0; q < s; ++q) {
+            v[q] += e[q];
+            cm = fmaxf(cm, fabsf(e[q]));
+            xm = fmaxf(xm, fabsf(v[q]));
+        }
+        if (cm <= 1e-7f * xm) break;
     }
-    pt_solve(t, s, e);
     for (int j = 0; j < t.p; ++j) t.bt[j] = 0.f;
     for (int c = 0; c < s; ++c) {
-        float bc = v[c] + e[c];
+        float bc = v[c];
         if (!__builtin_isfinite(bc)) return false;
         t.bt[t.ss[c]] = bc;
     }
@@ -367,11 +377,23 @@ __device__ bool pt_certificate(PT &t, int s, float *u, float *c, bool &unique)
         t.gd[j] = g;
     }
     uint32_t smask = 0;
+    double rhs[PMAX];
     for (int q = 0; q < s; ++q) {
         smask |= 1u << t.ss[q];
-        u[q] = (float)((double)t.lam * (double)sgn1(t.bt[t.ss[q]]) - t.gd[t.ss[q]]);
+        rhs[q] = (double)t.lam * (double)sgn1(t.bt[t.ss[q]]) - t.gd[t.ss[q]];
+        u[q] = (float)rhs[q];
     }
     pt_solve_t(t, s, u);
+    for (int it = 0; it < 2; ++it) {
+        float du[PMAX];
+        for (int c = 0; c < s; ++c) {
+            double acc = rhs[c];
+            for (int q = 0; q < s; ++q) acc -= (double)t.x(t.zs[q], t.ss[c]) * (double)u[q];
+            du[c] = (float)acc;
+        }
+        pt_solve_t(t, s, du);
+        for (int c = 0; c < s; ++c) u[c] += du[c];
+    }
     float umax = 0.f;
     for (int q = 0; q < s; ++q) umax = fmaxf(umax, fabsf(u[q]));
     bool viol = false;
@@ -450,22 +472,9 @@ __device__ int pt_finisher(PT &t, int &s, float &f, float *u, float *c, bool &un
             if (t.zf[i]) a = (i == zsel) ? -sgn1(usel) : 0.f;
             t.xd[i] = a;
         }
-        float bel = 0.f, at = 0.f, tot = 0.f;
-        for (int i = 0; i < n; ++i) {
-            float ax = fabsf(t.xd[i]), r = t.rv[i];
-            bool z = r == 0.f, neg = __builtin_signbit(r) != __builtin_signbit(t.xd[i]);
-            tot += ax;
-            at += z ? ax : 0.f;
-            bel += (!z && neg) ? ax : 0.f;
-        }
-        for (int j = 0; j < p; ++j) {
-            float wv = lam * fabsf(t.vd[j]), bj = t.bt[j];
-            bool z = bj == 0.f, neg = __builtin_signbit(bj) == __builtin_signbit(t.vd[j]);
-            tot += wv;
-            at += z ? wv : 0.f;
-            bel += (!z && neg) ? wv : 0.f;
-        }
-        const float need = 0.5f * tot - bel - at;
+        // the right slope of f along d at t = 0 is `best`; the minimiser is
+        // the first kink t > 0 whose cumulative weight reaches -best/2
+        const float need = -0.5f * best;
         if (!(need > 0.f)) return ST_NOTCERT;
         int m = 0;
         for (int i = 0; i < n; ++i) {
@@ -686,6 +695,8 @@ __device__ void pt_solve_item(PT &t, const SolveArgs &a, int s)
                         done = (double)fo - yu <= 2e-6 * fmax(1.0, (double)fo);
                     }
                     status = done ? ST_NONUNIQUE : ST_NOTCERT;
+                } else if (perturbed) {
+                    for (int i = 0; i < n; ++i) t.y[i] = t.yg[i]; // for the next path step
                 }
             }
             if (done) {

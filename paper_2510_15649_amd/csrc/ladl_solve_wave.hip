@@ -33,39 +33,49 @@ __device__ __forceinline__ float unif(float v) { return bitsf(__builtin_amdgcn_r
 
 __host__ __device__ constexpr int wave_ldn(int R) { return 64 * R + 1; }
 
-__host__ __device__ constexpr size_t wave_lds_floats(int R, int pmax)
+// LDS floats per wave: gd, [Xs, ys, rn when resident], best residuals,
+// A (pmax rows), 6 vectors, sa/sw, zs/ss/piv
+__host__ __device__ constexpr size_t wave_lds_floats(int R, int pmax, bool xg)
 {
-    return (size_t)pmax * wave_ldn(R) + 2 * (size_t)wave_ldn(R) + 32 * ALD + 6 * 32 + 64 /*gd*/ + 128 +
+    return 64 + (xg ? 0 : (size_t)(pmax + 2) * wave_ldn(R)) + 64 * (size_t)R + (size_t)pmax * ALD + 6 * 32 + 128 +
            3 * 32;
 }
+// global workspace floats per wave when X is not LDS-resident: Xs, ys, rn
+__host__ __device__ constexpr size_t wave_ws_floats(int R, int pmax) { return (size_t)(pmax + 2) * wave_ldn(R); }
 
-template <int R>
+template <int R, bool XG>
 struct Wave {
     static constexpr int LDN = wave_ldn(R);
-    float *Xs, *ys, *rn, *A, *vb, *vbb, *vca, *vd, *vg, *vt, *sa, *sw;
+    // Xs, ys, rn: LDS (XG false) or this wave's slice of a global workspace
+    float *Xs, *ys, *rn, *rbuf, *A, *vb, *vbb, *vca, *vd, *vg, *vt, *sa, *sw;
     double *gd;
     int *zs, *ss, *piv;
     int n, p, nslot;
     float lam, ynorm1;
+    float cav; // lane j: sum_i |x_ij|
     DevOpt opt;
     int c_sweeps, c_updates, c_probes, c_pivots;
 };
 
-template <int R>
-LADL_INL void carve(Wave<R> &w, float *smem, int pmax)
+template <int R, bool XG>
+LADL_INL void carve(Wave<R, XG> &w, float *smem, int pmax, float *ws)
 {
-    constexpr int LDN = Wave<R>::LDN;
+    constexpr int LDN = Wave<R, XG>::LDN;
     float *q = smem;
     w.gd = (double *)q; // first: the dynamic LDS base is 16-byte aligned
     q += 64;
-    w.Xs = q;
-    q += (size_t)pmax * LDN;
-    w.ys = q;
-    q += LDN;
-    w.rn = q;
-    q += LDN;
+    float *big = XG ? ws : q;
+    w.Xs = big;
+    big += (size_t)pmax * LDN;
+    w.ys = big;
+    big += LDN;
+    w.rn = big;
+    big += LDN;
+    if (!XG) q = big;
+    w.rbuf = q;
+    q += 64 * R;
     w.A = q;
-    q += 32 * ALD;
+    q += pmax * ALD;
     w.vb = q;
     q += 32;
     w.vbb = q;
@@ -89,13 +99,26 @@ LADL_INL void carve(Wave<R> &w, float *smem, int pmax)
     w.piv = (int *)q;
 }
 
+// After this wave writes its workspace (global memory when XG): the stores
+// complete, and L1 drops lines it may hold from before, so the wave's next
+// loads see what it wrote.  With LDS only the wave barrier is needed.
+template <bool XG>
+LADL_INL void ws_sync()
+{
+    if (XG) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
 // --------------------------------------------------------------------------
 // problem load: X row-major in HBM -> column-major in LDS (coalesced reads)
 // --------------------------------------------------------------------------
-template <int R>
-LADL_INL bool load_problem(Wave<R> &w, const float *__restrict__ X, const float *__restrict__ y)
+template <int R, bool XG>
+LADL_INL bool load_problem(Wave<R, XG> &w, const float *__restrict__ X, const float *__restrict__ y)
 {
-    constexpr int LDN = Wave<R>::LDN;
+    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id(), n = w.n, p = w.p, top = 64 * w.nslot;
     for (int j = 0; j < p; ++j)
         for (int i = n + l; i < top; i += 64) w.Xs[j * LDN + i] = 0.f;
@@ -121,7 +144,7 @@ LADL_INL bool load_problem(Wave<R> &w, const float *__restrict__ X, const float 
         w.ys[i] = v;
         finite = finite && __builtin_isfinite(v);
     }
-    __syncthreads();
+    ws_sync<XG>();
     for (int i = l; i < n; i += 64) {
         float s2 = 0.f;
         for (int j = 0; j < p; ++j) {
@@ -130,12 +153,15 @@ LADL_INL bool load_problem(Wave<R> &w, const float *__restrict__ X, const float 
         }
         w.rn[i] = sqrtf(s2);
     }
+    ws_sync<XG>();
     for (int j = 0; j < p; ++j) {
         float part = 0.f;
         for (int i = l; i < n; i += 64) part += fabsf(w.Xs[j * LDN + i]);
         float sj = wsum(part);
         if (l == j) w.vca[j] = sj;
+        if (l == j) w.cav = sj;
     }
+    if (l >= p) w.cav = 0.f;
     float yp = 0.f;
     for (int i = l; i < n; i += 64) yp += fabsf(w.ys[i]);
     w.ynorm1 = wsum(yp);
@@ -143,16 +169,16 @@ LADL_INL bool load_problem(Wave<R> &w, const float *__restrict__ X, const float 
     return ballot(!finite) == 0;
 }
 
-// r = y - X b with b in vb
-template <int R>
-LADL_INL void residuals(Wave<R> &w, float (&r)[R])
+// r = y - X b, b held one coefficient per lane (lane j: b_j)
+template <int R, bool XG>
+LADL_INL void residuals(Wave<R, XG> &w, float (&r)[R], float bv)
 {
-    constexpr int LDN = Wave<R>::LDN;
+    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id();
 #pragma unroll
     for (int k = 0; k < R; ++k) r[k] = (k < w.nslot) ? w.ys[64 * k + l] : 0.f;
     for (int j = 0; j < w.p; ++j) {
-        float bj = unif(w.vb[j]);
+        float bj = rdlane(bv, j);
         if (bj != 0.f) {
 #pragma unroll
             for (int k = 0; k < R; ++k)
@@ -161,16 +187,16 @@ LADL_INL void residuals(Wave<R> &w, float (&r)[R])
     }
 }
 
-template <int R>
-LADL_INL float objective(Wave<R> &w, const float (&r)[R], const float *bvec)
+// f = sum |r_i| + lambda sum |b_j|, b one coefficient per lane
+template <int R, bool XG>
+LADL_INL float objective(Wave<R, XG> &w, const float (&r)[R], float bval)
 {
     const int l = lane_id();
     float s = 0.f;
 #pragma unroll
     for (int k = 0; k < R; ++k) s += fabsf(r[k]);
-    float sb = (l < w.p) ? fabsf(bvec[l]) : 0.f;
-    float z = 0.f;
-    wsum3(s, sb, z);
+    float sb = (l < w.p) ? fabsf(bval) : 0.f;
+    wsum2(s, sb);
     return s + w.lam * sb;
 }
 
@@ -188,7 +214,7 @@ struct Sel {
     bool virt;
 };
 
-template <int R>
+template <int R, bool XG>
 LADL_INL Sel owner_of(const float (&a)[R], float av, float m)
 {
     const int l = lane_id();
@@ -212,15 +238,15 @@ LADL_INL Sel owner_of(const float (&a)[R], float av, float m)
     return s;
 }
 
-template <int R>
-LADL_INL Sel wselect(Wave<R> &w, const float (&a)[R], const float (&wt)[R], float av, float wv, float T,
-                       bool strict)
+template <int R, bool XG>
+LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&wt)[R], float av, float wv, float T,
+                       bool strict, float lo0, float cum0)
 {
     const int l = lane_id();
-    float lo = -1.f, hi = FINF, cum = 0.f;
+    float lo = lo0, hi = FINF, cum = cum0;
     auto reached = [&](float c) { return strict ? (c > T) : (c >= T); };
-    // Phase A: the next two distinct keys (small moves of a warm start)
-    for (int it = 0; it < 2; ++it) {
+    // Phase A: the next distinct keys one at a time (short moves)
+    for (int it = 0; it < 3; ++it) {
         float m = FINF;
 #pragma unroll
         for (int k = 0; k < R; ++k)
@@ -229,14 +255,14 @@ LADL_INL Sel wselect(Wave<R> &w, const float (&a)[R], const float (&wt)[R], floa
         m = wmin(m);
         if (m == FINF) {
             if (lo < 0.f) return Sel{FINF, 0, -1, false}; // no candidate at all
-            return owner_of<R>(a, av, lo);                 // weight exhausted by rounding
+            return owner_of<R, XG>(a, av, lo);                 // weight exhausted by rounding
         }
         float wm = 0.f;
 #pragma unroll
         for (int k = 0; k < R; ++k) wm += (a[k] == m) ? wt[k] : 0.f;
         wm += (av == m) ? wv : 0.f;
         wm = wsum(wm);
-        if (reached(cum + wm)) return owner_of<R>(a, av, m);
+        if (reached(cum + wm)) return owner_of<R, XG>(a, av, m);
         cum += wm;
         lo = m;
     }
@@ -306,11 +332,11 @@ LADL_INL Sel wselect(Wave<R> &w, const float (&a)[R], const float (&wt)[R], floa
             for (int k = 0; k < R; ++k) wm += (a[k] == m) ? wt[k] : 0.f;
             wm += (av == m) ? wv : 0.f;
             wm = wsum(wm);
-            if (reached(cum + wm) || m == hi) return owner_of<R>(a, av, m);
+            if (reached(cum + wm) || m == hi) return owner_of<R, XG>(a, av, m);
             cum += wm;
             lo = m;
         }
-        return owner_of<R>(a, av, hi);
+        return owner_of<R, XG>(a, av, hi);
     }
     // Phase C: compact the <= 64 keys of (lo, hi], sort, scan
     int base = 0;
@@ -349,88 +375,159 @@ LADL_INL Sel wselect(Wave<R> &w, const float (&a)[R], const float (&wt)[R], floa
         m = rdlane(key, base - 1); // rounding: take the last key
     else
         m = (hi < FINF) ? hi : lo;
-    return owner_of<R>(a, av, m);
+    return owner_of<R, XG>(a, av, m);
 }
 
 // --------------------------------------------------------------------------
-// H4: exact minimisation of f along axis j (weighted median of the kinks)
+// H4: exact minimisation of f along axis j: the lower weighted median of the
+// kinks t_i = b_j + r_i/x_ij (weight |x_ij|) and 0 (weight lambda).
+// One pass over the rows classifies every kink against the current b_j by
+// signs alone (below: r_i x_ij < 0, at: r_i = 0) and records, per lane, the
+// nearest kink on each side with its weight.  After the two weight sums the
+// direction is known; most moves reach only the nearest kink, decided by
+// one wave minimum.  Longer moves continue in wselect.
 // --------------------------------------------------------------------------
-template <int R>
-LADL_INL bool coord_update(Wave<R> &w, float (&r)[R], int j)
+template <int R, bool XG>
+LADL_INL bool coord_update(Wave<R, XG> &w, float (&r)[R], float &bv, int j, const float (&x)[R])
 {
-    constexpr int LDN = Wave<R>::LDN;
     const int l = lane_id();
-    const float *xc = w.Xs + j * LDN;
-    float x[R];
-    float bel = 0.f, at = 0.f, abv = 0.f;
+    float a[R];
+    uint32_t negb = 0;
+    float bel = 0.f, at = 0.f;
+    float umin = FINF, uw = 0.f, dmin = FINF, dw = 0.f;
+    int uk = 0, dk = 0;
+    bool utie = false, dtie = false;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        x[k] = (k < w.nslot) ? xc[64 * k + l] : 0.f;
-        float rr = r[k], ax = fabsf(x[k]);
-        bool z = (rr == 0.f);
-        bool neg = __builtin_signbit(rr) != __builtin_signbit(x[k]);
+        const float rr = r[k], ax = fabsf(x[k]);
+        const bool z = (rr == 0.f);
+        const bool neg = (fbits(rr) ^ fbits(x[k])) < 0;
+        const float ak = (z || ax == 0.f) ? FINF : fabsf(rr) * __builtin_amdgcn_rcpf(ax);
+        a[k] = ak;
+        negb |= neg ? (1u << k) : 0u;
         at += z ? ax : 0.f;
         bel += (!z && neg) ? ax : 0.f;
-        abv += (!z && !neg) ? ax : 0.f;
+        const bool dn = neg && ak < dmin, up = !neg && ak < umin;
+        dtie = dtie || (neg && ak == dmin && ak < FINF);
+        utie = utie || (!neg && ak == umin && ak < FINF);
+        dmin = dn ? ak : dmin;
+        dw = dn ? ax : dw;
+        dk = dn ? k : dk;
+        umin = up ? ak : umin;
+        uw = up ? ax : uw;
+        uk = up ? k : uk;
     }
-    const float bj = unif(w.vb[j]);
-    wsum3(bel, at, abv);
+    const float bj = rdlane(bv, j);
+    float dminw = dmin, uminw = umin;
+    wsum2_min2(bel, at, dminw, uminw);
     const float lam = w.lam;
-    const float W = (bel + at) + (abv + lam);
+    const float W = rdlane(w.cav, j) + lam;
     if (!(W > 0.f)) return false;
     const float belT = bel + ((bj > 0.f) ? lam : 0.f);
     const float atT = at + ((bj == 0.f) ? lam : 0.f);
     const float half = 0.5f * W;
-    int dir;
+    bool down;
     if (belT >= half)
-        dir = -1;
+        down = true;
     else if (belT + atT < half)
-        dir = 1;
+        down = false;
     else
-        return false;
-    float a[R], wt[R];
+        return false; // b_j is already the minimiser
+    const float T = down ? (belT - half) : (half - belT - atT);
+    auto reached = [&](float c) { return down ? (c > T) : (c >= T); };
+    const float smin = down ? dmin : umin;
+    const float sw_ = down ? dw : uw;
+    const int sk = down ? dk : uk;
+    const bool stie = down ? dtie : utie;
+    const bool lcand = (lam > 0.f) && (down ? (bj > 0.f) : (bj < 0.f));
+    const float al = fabsf(bj);
+    const float m1 = down ? dminw : uminw;
+    if (!(m1 < FINF) && !lcand) return false;
+    const float mm = lcand ? fminf(m1, al) : m1;
+    // weight of the nearest kink(s)
+    const uint64_t ob = ballot(smin == mm);
+    float wm;
+    if (popc64(ob) > 1 || ballot(stie && smin == mm)) {
+        float part = 0.f;
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        float rr = r[k], xk = x[k];
-        bool neg = __builtin_signbit(rr) != __builtin_signbit(xk);
-        bool cand = (xk != 0.f) && (rr != 0.f) && (dir < 0 ? neg : !neg);
-        float ax = fabsf(xk);
-        a[k] = cand ? fabsf(rr) * __builtin_amdgcn_rcpf(ax) : FINF;
-        wt[k] = cand ? ax : 0.f;
+        for (int k = 0; k < R; ++k) {
+            const bool side = (((negb >> k) & 1u) != 0u) == down;
+            part += (side && a[k] == mm) ? fabsf(x[k]) : 0.f;
+        }
+        wm = wsum(part);
+    } else {
+        wm = ob ? rdlane(sw_, first_lane(ob)) : 0.f;
     }
-    const bool lcand = (lam > 0.f) && (dir < 0 ? (bj > 0.f) : (bj < 0.f));
-    const float av = (l == 0 && lcand) ? fabsf(bj) : FINF;
-    const float wv = (l == 0 && lcand) ? lam : 0.f;
-    const float T = (dir < 0) ? (belT - half) : (half - belT - atT);
-    Sel s = wselect<R>(w, a, wt, av, wv, T, dir < 0);
-    float nb = s.virt ? 0.f : ((dir < 0) ? bj - s.a : bj + s.a);
-    float d = nb - bj;
+    if (lcand && al == mm) wm += lam;
+    float nb;
+    int olane = -1, oslot = -1;
+    bool virt;
+    if (reached(wm)) {
+        virt = (ob == 0);
+        if (!virt) {
+            olane = first_lane(ob);
+            oslot = rdlane(sk, olane);
+        }
+        nb = virt ? 0.f : (down ? bj - mm : bj + mm);
+    } else {
+        float ac[R], wt[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const bool side = (((negb >> k) & 1u) != 0u) == down;
+            ac[k] = side ? a[k] : FINF;
+            wt[k] = side ? fabsf(x[k]) : 0.f;
+        }
+        const float av = (l == 0 && lcand) ? al : FINF;
+        const float wv = (l == 0 && lcand) ? lam : 0.f;
+        Sel sl = wselect<R, XG>(w, ac, wt, av, wv, T, down, mm, wm);
+        if (!(sl.a < FINF)) return false;
+        virt = sl.virt;
+        olane = sl.lane;
+        oslot = sl.slot;
+        nb = virt ? 0.f : (down ? bj - sl.a : bj + sl.a);
+    }
+    const float d = nb - bj;
     if (d == 0.f || !__builtin_isfinite(d)) return false;
 #pragma unroll
     for (int k = 0; k < R; ++k) r[k] = fmaf(-x[k], d, r[k]);
-    if (!s.virt && l == s.lane) {
+    if (!virt && l == olane) {
 #pragma unroll
         for (int k = 0; k < R; ++k)
-            if (k == s.slot) r[k] = 0.f; // the median row is now on its hyperplane
+            if (k == oslot) r[k] = 0.f; // the median row is now on its hyperplane
     }
-    if (l == 0) w.vb[j] = nb;
-    __syncthreads();
+    bv = (l == j) ? nb : bv;
     return true;
 }
 
 // H5: cyclic sweeps, axis `frozen` held fixed
-template <int R>
-LADL_INL float ccd(Wave<R> &w, float (&r)[R], int frozen, float f)
+template <int R, bool XG>
+LADL_INL float ccd(Wave<R, XG> &w, float (&r)[R], float &bv, int frozen, float f)
 {
+    constexpr int LDN = Wave<R, XG>::LDN;
+    const int l = lane_id(), p = w.p;
+    if (p == 1 && frozen == 0) return f;
+    // column j's values are loaded while column j-1 is updated
+    int j = (frozen == 0) ? 1 : 0;
+    float x[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) x[k] = (k < w.nslot) ? w.Xs[j * LDN + 64 * k + l] : 0.f;
     for (int sw = 0; sw < w.opt.max_sweeps; ++sw) {
         bool changed = false;
-        for (int j = 0; j < w.p; ++j) {
-            if (j == frozen) continue;
-            changed |= coord_update<R>(w, r, j);
+        for (int u = 0; u < p; ++u) {
+            if (u == frozen) continue;
+            int jn = u + 1;
+            if (jn == frozen) ++jn;
+            if (jn >= p) jn = (frozen == 0) ? 1 : 0;
+            float xn[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) xn[k] = (k < w.nslot) ? w.Xs[jn * LDN + 64 * k + l] : 0.f;
+            changed |= coord_update<R, XG>(w, r, bv, u, x);
             w.c_updates++;
+#pragma unroll
+            for (int k = 0; k < R; ++k) x[k] = xn[k];
         }
         w.c_sweeps++;
-        float fn = objective<R>(w, r, w.vb);
+        float fn = objective<R, XG>(w, r, bv);
         bool stop = !changed || (f - fn <= w.opt.tol_f * fn);
         f = fn;
         if (stop) break;
@@ -449,10 +546,10 @@ LADL_INL float ccd(Wave<R> &w, float (&r)[R], int frozen, float f)
 // duplicated row, say) is passed over (modified Gram-Schmidt, basis kept in
 // the A area of LDS).  Writes zs/ss and the per-lane Z bits; returns |S|
 // (= |Z|) or -1.
-template <int R>
-LADL_INL int choose_vertex(Wave<R> &w, const float (&r)[R], uint32_t &zbits)
+template <int R, bool XG>
+LADL_INL int choose_vertex(Wave<R, XG> &w, const float (&r)[R], float bv, uint32_t &zbits)
 {
-    constexpr int LDN = Wave<R>::LDN;
+    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id(), p = w.p;
     float dist[R];
 #pragma unroll
@@ -460,7 +557,7 @@ LADL_INL int choose_vertex(Wave<R> &w, const float (&r)[R], uint32_t &zbits)
         float nr = (k < w.nslot) ? w.rn[64 * k + l] : 0.f;
         dist[k] = (nr > 0.f) ? fabsf(r[k]) / nr : FINF;
     }
-    const float dv = (l < p) ? fabsf(w.vb[l]) : FINF;
+    const float dv = (l < p) ? fabsf(bv) : FINF;
     float *Q = w.A;
     zbits = 0;
     uint32_t seen = 0;
@@ -593,10 +690,10 @@ LADL_INL float lu_solve_t(const float *A, const int *piv, int s, float v)
 // Vertex (zs, ss, s): A = X_{Z,S} factored in LDS, b_S = A^{-1} y_Z with
 // one refinement step (residual in fp64), b into vt, residuals into rv
 // (exact zeros on Z), objective into f.  Lane c returns b_{S_c} in bS.
-template <int R>
-LADL_INL bool vertex_eval(Wave<R> &w, float (&rv)[R], uint32_t zbits, int s, float &f)
+template <int R, bool XG>
+LADL_INL bool vertex_eval(Wave<R, XG> &w, float (&rv)[R], uint32_t zbits, int s, float &f)
 {
-    constexpr int LDN = Wave<R>::LDN;
+    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id();
     for (int q = 0; q < s; ++q) {
         int zq = uni(w.zs[q]);
@@ -607,13 +704,18 @@ LADL_INL bool vertex_eval(Wave<R> &w, float (&rv)[R], uint32_t zbits, int s, flo
     const int zl = (l < s) ? w.zs[l] : 0;
     const float yz = (l < s) ? w.ys[zl] : 0.f;
     float xs = lu_solve(w.A, w.piv, s, yz);
-    double acc = (double)yz;
-    for (int c = 0; c < s; ++c) {
-        float xc = rdlane(xs, c);
-        int jc = uni(w.ss[c]);
-        if (l < s) acc -= (double)w.Xs[jc * LDN + zl] * (double)xc;
+    // mixed-precision refinement: residual y_Z - X_{Z,S} b_S in fp64
+    for (int it = 0; it < 3; ++it) {
+        double acc = (double)yz;
+        for (int c = 0; c < s; ++c) {
+            float xc = rdlane(xs, c);
+            int jc = uni(w.ss[c]);
+            if (l < s) acc -= (double)w.Xs[jc * LDN + zl] * (double)xc;
+        }
+        const float corr = lu_solve(w.A, w.piv, s, (l < s) ? (float)acc : 0.f);
+        xs += corr;
+        if (wmax(fabsf(corr)) <= 1e-7f * wmax(fabsf(xs))) break;
     }
-    xs += lu_solve(w.A, w.piv, s, (l < s) ? (float)acc : 0.f);
     if (ballot(l < s && !__builtin_isfinite(xs))) return false;
     if (l < w.p) w.vt[l] = 0.f;
     __syncthreads();
@@ -631,18 +733,18 @@ LADL_INL bool vertex_eval(Wave<R> &w, float (&rv)[R], uint32_t zbits, int s, flo
 #pragma unroll
     for (int k = 0; k < R; ++k)
         if ((zbits >> k) & 1u) rv[k] = 0.f;
-    f = objective<R>(w, rv, w.vt);
+    f = objective<R, XG>(w, rv, (l < w.p) ? w.vt[l] : 0.f);
     return true;
 }
 
 // LP optimality certificate at the evaluated vertex (A holds its LU):
 // u_i = sign(r_i) off Z, X_{Z,S}^T u_Z = lambda sign(b_S) - X_{Zc,S}^T u_Zc,
 // c = X^T u.  Lane q returns u_{Z_q} in u, lane j returns c_j in c.
-template <int R>
-LADL_INL bool certificate(Wave<R> &w, const float (&rv)[R], uint32_t zbits, int s, float &u, float &c,
+template <int R, bool XG>
+LADL_INL bool certificate(Wave<R, XG> &w, const float (&rv)[R], uint32_t zbits, int s, float &u, float &c,
                             bool &unique)
 {
-    constexpr int LDN = Wave<R>::LDN;
+    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id(), p = w.p;
     double g = 0.0;
     for (int j = 0; j < p; ++j) {
@@ -657,12 +759,23 @@ LADL_INL bool certificate(Wave<R> &w, const float (&rv)[R], uint32_t zbits, int 
     __syncthreads();
     uint32_t smask = 0;
     for (int q = 0; q < s; ++q) smask |= 1u << uni(w.ss[q]);
-    float rhs = 0.f;
+    double rhs = 0.0;
+    int jq = 0;
     if (l < s) {
-        int jq = w.ss[l];
-        rhs = (float)((double)w.lam * (double)sgnf(w.vt[jq]) - w.gd[jq]);
+        jq = w.ss[l];
+        rhs = (double)w.lam * (double)sgnf(w.vt[jq]) - w.gd[jq];
     }
-    u = lu_solve_t(w.A, w.piv, s, rhs);
+    u = lu_solve_t(w.A, w.piv, s, (float)rhs);
+    // refinement: residual rhs - X_{Z,S}^T u in fp64
+    for (int it = 0; it < 2; ++it) {
+        double acc = rhs;
+        for (int q = 0; q < s; ++q) {
+            float uq = rdlane(u, q);
+            int zq = uni(w.zs[q]);
+            if (l < s) acc -= (double)w.Xs[jq * LDN + zq] * (double)uq;
+        }
+        u += lu_solve_t(w.A, w.piv, s, (l < s) ? (float)acc : 0.f);
+    }
     double cj = g;
     for (int q = 0; q < s; ++q) {
         float uq = rdlane(u, q);
@@ -693,16 +806,16 @@ LADL_INL bool certificate(Wave<R> &w, const float (&rv)[R], uint32_t zbits, int 
 // release the most violated constraint, move to the minimum of f along the
 // edge (again a weighted median) and let the kink reached join the vertex.
 // Returns the status; u (lane q) and c (lane j) hold the last dual values.
-template <int R>
-LADL_INL int finisher(Wave<R> &w, float (&rv)[R], uint32_t &zbits, int &s, float &f, float &u, float &c,
+template <int R, bool XG>
+LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, float &f, float &u, float &c,
                       bool &unique, int maxp)
 {
-    constexpr int LDN = Wave<R>::LDN;
+    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id(), p = w.p;
     const float lam = w.lam;
     for (int it = 0;; ++it) {
-        if (!vertex_eval<R>(w, rv, zbits, s, f)) return ST_NOTCERT;
-        if (certificate<R>(w, rv, zbits, s, u, c, unique)) return unique ? ST_CERTIFIED : ST_NONUNIQUE;
+        if (!vertex_eval<R, XG>(w, rv, zbits, s, f)) return ST_NOTCERT;
+        if (certificate<R, XG>(w, rv, zbits, s, u, c, unique)) return unique ? ST_CERTIFIED : ST_NONUNIQUE;
         if (it >= maxp) return ST_MAXITER;
         uint32_t smask = 0;
         for (int q = 0; q < s; ++q) smask |= 1u << uni(w.ss[q]);
@@ -749,29 +862,13 @@ LADL_INL int finisher(Wave<R> &w, float (&rv)[R], uint32_t &zbits, int &s, float
         for (int k = 0; k < R; ++k)
             if ((zbits >> k) & 1u) xd[k] = (64 * k + l == zsel) ? -sgnf(usel) : 0.f;
         // f(b + t d) = sum |r_i - t xd_i| + lam sum |b_j + t d_j|: kinks at
-        // r_i/xd_i (weight |xd_i|) and -b_j/d_j (weight lam |d_j|)
-        float bel = 0.f, at = 0.f, tot = 0.f;
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            float ax = fabsf(xd[k]);
-            bool z = rv[k] == 0.f;
-            bool neg = __builtin_signbit(rv[k]) != __builtin_signbit(xd[k]);
-            tot += ax;
-            at += z ? ax : 0.f;
-            bel += (!z && neg) ? ax : 0.f;
-        }
+        // r_i/xd_i (weight |xd_i|) and -b_j/d_j (weight lam |d_j|).  Its
+        // right slope at t = 0 is m (1 - |u_i0| or lam - |c_j0|, from the
+        // fp64 dual sums), so the minimiser is the first kink t > 0 whose
+        // cumulative weight reaches -m/2.
         const float dl = (l < p) ? w.vd[l] : 0.f;
         const float bl = (l < p) ? w.vt[l] : 0.f;
-        {
-            float wvv = lam * fabsf(dl);
-            bool z = bl == 0.f;
-            bool neg = __builtin_signbit(bl) == __builtin_signbit(dl); // -b/d < 0
-            tot += wvv;
-            at += z ? wvv : 0.f;
-            bel += (!z && neg) ? wvv : 0.f;
-        }
-        wsum3(bel, at, tot);
-        const float need = 0.5f * tot - bel - at;
+        const float need = -0.5f * m;
         if (!(need > 0.f)) return ST_NOTCERT;
         float a[R], wt[R];
 #pragma unroll
@@ -786,7 +883,7 @@ LADL_INL int finisher(Wave<R> &w, float (&rv)[R], uint32_t &zbits, int &s, float
                           __builtin_signbit(bl) != __builtin_signbit(dl);
         const float av = vpos ? fabsf(bl) / fabsf(dl) : FINF;
         const float wv = vpos ? lam * fabsf(dl) : 0.f;
-        Sel sr = wselect<R>(w, a, wt, av, wv, need, false);
+        Sel sr = wselect<R, XG>(w, a, wt, av, wv, need, false, -1.f, 0.f);
         if (!(sr.a > 0.f) || sr.a == FINF) return ST_NOTCERT;
         // new vertex
         if (type1) {
@@ -831,26 +928,26 @@ LADL_INL int finisher(Wave<R> &w, float (&rv)[R], uint32_t &zbits, int &s, float
 // Degenerate vertices (more rows on their hyperplanes than active axes,
 // e.g. duplicated rows) can make the edge steps cycle; a tiny deterministic
 // perturbation of y separates such rows.
-template <int R>
-LADL_INL void perturb_y(Wave<R> &w)
+template <int R, bool XG>
+LADL_INL void perturb_y(Wave<R, XG> &w)
 {
     const int l = lane_id();
     const float ybar = w.ynorm1 / (float)w.n;
     for (int i = l; i < w.n; i += 64) w.ys[i] += PERTURB_REL * (fabsf(w.ys[i]) + ybar) * perturb_dir(i);
-    __syncthreads();
+    ws_sync<XG>();
 }
 
 // objective of b (in bvec) recomputed with fp64 residuals and sums
-template <int R>
-LADL_INL float objective64(Wave<R> &w, const float *bvec)
+template <int R, bool XG>
+LADL_INL float objective64(Wave<R, XG> &w, float bval)
 {
-    constexpr int LDN = Wave<R>::LDN;
+    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id();
     double acc[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) acc[k] = (k < w.nslot) ? (double)w.ys[64 * k + l] : 0.0;
     for (int j = 0; j < w.p; ++j) {
-        double bj = (double)unif(bvec[j]);
+        double bj = (double)rdlane(bval, j);
         if (bj != 0.0) {
 #pragma unroll
             for (int k = 0; k < R; ++k)
@@ -860,15 +957,15 @@ LADL_INL float objective64(Wave<R> &w, const float *bvec)
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < R; ++k) s += fabs(acc[k]);
-    s += (l < w.p) ? (double)w.lam * fabs((double)bvec[l]) : 0.0;
+    s += (l < w.p) ? (double)w.lam * fabs((double)bval) : 0.0;
     return (float)wsum_d(s);
 }
 
 // --------------------------------------------------------------------------
 // one solve (all its path steps)
 // --------------------------------------------------------------------------
-template <int R>
-LADL_INL void solve_item(Wave<R> &w, const SolveArgs &a, int s)
+template <int R, bool XG>
+LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
 {
     const int l = lane_id();
     const int k = a.problem ? a.problem[s] : s;
@@ -877,7 +974,7 @@ LADL_INL void solve_item(Wave<R> &w, const SolveArgs &a, int s)
     w.p = a.p_arr[k];
     w.nslot = (w.n + 63) >> 6;
     const int p = w.p;
-    const bool finite = load_problem<R>(w, a.X + a.x_off[k], a.y + r0);
+    const bool finite = load_problem<R, XG>(w, a.X + a.x_off[k], a.y + r0);
     const int64_t bbase = (int64_t)a.path_len * a.b_off[s];
     // starting point
     float b0 = 0.f;
@@ -885,9 +982,9 @@ LADL_INL void solve_item(Wave<R> &w, const SolveArgs &a, int s)
         b0 = (l < p) ? a.b_out[bbase + (int64_t)(a.t0 - 1) * p + l] : 0.f;
     else if (a.b_init)
         b0 = (l < p) ? a.b_init[a.b_off[s] + l] : 0.f;
-    if (l < 32) w.vb[l] = (l < p && __builtin_isfinite(b0)) ? b0 : 0.f;
-    __syncthreads();
-    float r[R], rb[R], rv[R];
+    float bv = (l < p && __builtin_isfinite(b0)) ? b0 : 0.f; // lane j holds b_j
+    float bbv = bv;                                           // best point of the chop
+    float r[R], rv[R];
     for (int t = a.t0; t < a.t1; ++t) {
         const int64_t o = (int64_t)s * a.path_len + t;
         float *bout = a.b_out + bbase + (int64_t)t * p;
@@ -898,13 +995,12 @@ LADL_INL void solve_item(Wave<R> &w, const SolveArgs &a, int s)
         int zcount = -1; // vertex rows to report (-1: none)
         if (!finite || !(lam_in >= 0.f)) {
             status = finite ? ST_BADLAMBDA : ST_NONFINITE;
-            if (l < p) w.vb[l] = 0.f;
-            __syncthreads();
+            bv = 0.f;
             fout = __builtin_nanf("");
         } else {
             w.lam = fmaxf(lam_in, w.opt.lambda_min);
-            residuals<R>(w, r);
-            float f = objective<R>(w, r, w.vb);
+            residuals<R, XG>(w, r, bv);
+            float f = objective<R, XG>(w, r, bv);
             status = ST_NOTCERT;
             bool done = false, unique = false, have_vertex = false;
             uint32_t zbits = 0;
@@ -918,15 +1014,15 @@ LADL_INL void solve_item(Wave<R> &w, const SolveArgs &a, int s)
             int frozen = -1, round = 0, kax = 0;
             float fbest = FINF;
             for (;;) {
-                f = ccd<R>(w, r, frozen, f); // the only CCD call site
+                f = ccd<R, XG>(w, r, bv, frozen, f); // the only CCD call site
                 float sprobe = 0.f;
                 bool more;
                 if (phase == 0) {
                     if (snap) {
-                        vs = choose_vertex<R>(w, r, zbits);
+                        vs = choose_vertex<R, XG>(w, r, bv, zbits);
                         have_vertex = vs >= 0;
                         if (have_vertex) {
-                            int st = finisher<R>(w, rv, zbits, vs, fv, u, c, unique, 0);
+                            int st = finisher<R, XG>(w, rv, zbits, vs, fv, u, c, unique, 0);
                             if (st == ST_CERTIFIED || st == ST_NONUNIQUE) {
                                 status = st;
                                 done = true;
@@ -936,47 +1032,45 @@ LADL_INL void solve_item(Wave<R> &w, const SolveArgs &a, int s)
                     }
                     if (round >= rounds) break;
                     if (round == 0) {
-                        float bl = (l < p) ? fabsf(w.vb[l]) : -1.f;
+                        float bl = (l < p) ? fabsf(bv) : -1.f;
                         float bm = wmax(bl);
                         kax = first_lane(ballot(l < p && bl == bm));
                     } else {
                         kax = (kax + 1) % p;
                     }
                     ++round;
-                    if (l < p) w.vbb[l] = w.vb[l];
+                    bbv = bv;
 #pragma unroll
-                    for (int kk = 0; kk < R; ++kk) rb[kk] = r[kk];
+                    for (int kk = 0; kk < R; ++kk)
+                        if (kk < w.nslot) w.rbuf[64 * kk + l] = r[kk];
                     fbest = f;
-                    __syncthreads();
-                    chop_init(q, unif(w.vbb[kax]), f, B);
+                    chop_init(q, rdlane(bbv, kax), f, B);
                     more = chop_next(q, 0.f, sprobe, w.opt);
                 } else {
                     w.c_probes++;
                     if (f < fbest) {
                         fbest = f;
-                        if (l < p) w.vbb[l] = w.vb[l];
+                        bbv = bv;
 #pragma unroll
-                        for (int kk = 0; kk < R; ++kk) rb[kk] = r[kk];
-                        __syncthreads();
+                        for (int kk = 0; kk < R; ++kk)
+                            if (kk < w.nslot) w.rbuf[64 * kk + l] = r[kk];
                     }
                     more = chop_next(q, f, sprobe, w.opt);
                 }
                 // next CCD starts from the best point; a probe sets b_kax := s
-                if (l < p) w.vb[l] = w.vbb[l];
+                bv = bbv;
 #pragma unroll
-                for (int kk = 0; kk < R; ++kk) r[kk] = rb[kk];
-                __syncthreads();
+                for (int kk = 0; kk < R; ++kk) r[kk] = (kk < w.nslot) ? w.rbuf[64 * kk + l] : 0.f;
                 if (more) {
-                    const float d = sprobe - unif(w.vbb[kax]);
+                    const float d = sprobe - rdlane(bbv, kax);
                     if (d != 0.f) {
-                        constexpr int LDN = Wave<R>::LDN;
+                        constexpr int LDN = Wave<R, XG>::LDN;
 #pragma unroll
                         for (int kk = 0; kk < R; ++kk)
                             if (kk < w.nslot) r[kk] = fmaf(-w.Xs[kax * LDN + 64 * kk + l], d, r[kk]);
                     }
-                    if (l == 0) w.vb[kax] = sprobe;
-                    __syncthreads();
-                    f = objective<R>(w, r, w.vb);
+                    bv = (l == kax) ? sprobe : bv;
+                    f = objective<R, XG>(w, r, bv);
                     frozen = kax;
                     phase = 1;
                 } else {
@@ -990,10 +1084,10 @@ LADL_INL void solve_item(Wave<R> &w, const SolveArgs &a, int s)
                 bool perturbed = false;
                 for (int attempt = 0; attempt < 2 && !done; ++attempt) {
                     if (attempt == 1) {
-                        perturb_y<R>(w);
+                        perturb_y<R, XG>(w);
                         perturbed = true;
                     }
-                    status = finisher<R>(w, rv, zbits, vs, fv, u, c, unique, maxp);
+                    status = finisher<R, XG>(w, rv, zbits, vs, fv, u, c, unique, maxp);
                     done = (status == ST_CERTIFIED || status == ST_NONUNIQUE);
                 }
                 if (done && perturbed) {
@@ -1006,33 +1100,37 @@ LADL_INL void solve_item(Wave<R> &w, const SolveArgs &a, int s)
                     for (int kk = 0; kk < R; ++kk) sg[kk] = sgnf(rv[kk]);
                     const float *yg = a.y + r0;
                     for (int i = l; i < w.n; i += 64) w.ys[i] = yg[i];
-                    __syncthreads();
+                    ws_sync<XG>();
                     double yu = 0.0;
 #pragma unroll
                     for (int kk = 0; kk < R; ++kk)
                         if (kk < w.nslot) yu += (double)w.ys[64 * kk + l] * (double)sg[kk];
                     if (l < vs) yu += (double)w.ys[w.zs[l]] * (double)u;
                     yu = wsum_d(yu);
-                    done = vertex_eval<R>(w, rv, zbits, vs, fv);
+                    done = vertex_eval<R, XG>(w, rv, zbits, vs, fv);
                     if (done) {
-                        float fo = objective64<R>(w, w.vt);
+                        float fo = objective64<R, XG>(w, (l < p) ? w.vt[l] : 0.f);
                         done = (double)fo - yu <= 2e-6 * fmax(1.0, (double)fo);
                     }
                     status = done ? ST_NONUNIQUE : ST_NOTCERT;
+                } else if (perturbed) {
+                    // failed even when perturbed: put y back for the next path step
+                    const float *yg = a.y + r0;
+                    for (int i = l; i < w.n; i += 64) w.ys[i] = yg[i];
+                    ws_sync<XG>();
                 }
             }
             if (done) {
-                if (l < p) w.vb[l] = w.vt[l];
+                bv = (l < p) ? w.vt[l] : 0.f;
                 zcount = vs;
-                __syncthreads();
             } else if (!snap) {
                 status = ST_MAXITER;
             }
-            fout = objective64<R>(w, w.vb);
+            fout = objective64<R, XG>(w, bv);
         }
         // outputs
-        if (l < p) bout[l] = w.vb[l];
-        uint64_t act = ballot(l < p && w.vb[l] != 0.f);
+        if (l < p) bout[l] = bv;
+        uint64_t act = ballot(l < p && bv != 0.f);
         if (l == 0) {
             a.obj_out[o] = fout;
             a.active_out[o] = (uint32_t)act;
@@ -1058,12 +1156,19 @@ LADL_INL void solve_item(Wave<R> &w, const SolveArgs &a, int s)
     }
 }
 
-template <int R>
-__global__ __launch_bounds__(64) void k_wave(SolveArgs a)
+// occupancy target (waves per SIMD) the register allocation must allow;
+// 0 leaves the choice to the compiler
+#ifndef LADL_WAVES_PER_EU
+#define LADL_WAVES_PER_EU 0
+#endif
+
+template <int R, bool XG>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LADL_WAVES_PER_EU > 0 ? LADL_WAVES_PER_EU : 1)))
+void k_wave(SolveArgs a)
 {
     extern __shared__ float smem[];
-    Wave<R> w;
-    carve<R>(w, smem, a.pmax);
+    Wave<R, XG> w;
+    carve<R, XG>(w, smem, a.pmax, XG ? a.gws + (int64_t)blockIdx.x * a.gws_stride : nullptr);
     w.opt = a.opt;
     const int l = lane_id();
     for (;;) {
@@ -1071,7 +1176,7 @@ __global__ __launch_bounds__(64) void k_wave(SolveArgs a)
         if (l == 0) q = atomicAdd(a.counter, 1);
         q = rdlane(q, 0);
         if (q >= a.num_items) break;
-        solve_item<R>(w, a, a.order[q]);
+        solve_item<R, XG>(w, a, a.order[q]);
     }
 }
 
@@ -1081,7 +1186,8 @@ __global__ void k_reset(int32_t *c, int n)
     if (i < n) c[i] = 0;
 }
 
-size_t wave_lds_bytes(int R, int pmax) { return 4 * wave_lds_floats(R, pmax); }
+size_t wave_lds_bytes(int R, int pmax, bool xg) { return 4 * wave_lds_floats(R, pmax, xg); }
+size_t wave_ws_floats_host(int R, int pmax) { return wave_ws_floats(R, pmax); }
 
 hipError_t launch_reset(int32_t *counters, int n, hipStream_t s)
 {
@@ -1089,52 +1195,143 @@ hipError_t launch_reset(int32_t *counters, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int R>
+template <int R, bool XG>
 static hipError_t launch_wave_t(const SolveArgs &a, int grid, hipStream_t s)
 {
-    size_t lds = wave_lds_bytes(R, a.pmax);
+    size_t lds = wave_lds_bytes(R, a.pmax, XG);
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_wave<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024);
-        if (e != hipSuccess) return e;
+        // allow dynamic LDS beyond the default limit; harmless if refused
+        (void)hipFuncSetAttribute((const void *)k_wave<R, XG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL(k_wave<R>, dim3(grid), dim3(64), lds, s, a);
+    hipLaunchKernelGGL((k_wave<R, XG>), dim3(grid), dim3(64), lds, s, a);
     return hipGetLastError();
 }
 
-template <int R>
+template <int R, bool XG>
 static int max_blocks_t(int pmax)
 {
     int nb = 0;
-    size_t lds = wave_lds_bytes(R, pmax);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_wave<R>, 64, lds) != hipSuccess) return 0;
+    size_t lds = wave_lds_bytes(R, pmax, XG);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_wave<R, XG>, 64, lds) != hipSuccess) return 0;
     return nb;
 }
 
-hipError_t launch_wave(int R, const SolveArgs &a, int grid, hipStream_t s)
+hipError_t launch_wave(int R, bool xg, const SolveArgs &a, int grid, hipStream_t s)
 {
+    if (xg) {
+        switch (R) {
+        case 1: return launch_wave_t<1, true>(a, grid, s);
+        case 2: return launch_wave_t<2, true>(a, grid, s);
+        case 4: return launch_wave_t<4, true>(a, grid, s);
+        case 8: return launch_wave_t<8, true>(a, grid, s);
+        case 16: return launch_wave_t<16, true>(a, grid, s);
+        case 32: return launch_wave_t<32, true>(a, grid, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (R) {
-    case 1: return launch_wave_t<1>(a, grid, s);
-    case 2: return launch_wave_t<2>(a, grid, s);
-    case 4: return launch_wave_t<4>(a, grid, s);
-    case 8: return launch_wave_t<8>(a, grid, s);
-    case 16: return launch_wave_t<16>(a, grid, s);
+    case 1: return launch_wave_t<1, false>(a, grid, s);
+    case 2: return launch_wave_t<2, false>(a, grid, s);
+    case 4: return launch_wave_t<4, false>(a, grid, s);
+    case 8: return launch_wave_t<8, false>(a, grid, s);
+    case 16: return launch_wave_t<16, false>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-int wave_max_blocks_per_cu(int R, int pmax)
+int wave_max_blocks_per_cu(int R, int pmax, bool xg)
 {
+    if (xg) {
+        switch (R) {
+        case 1: return max_blocks_t<1, true>(pmax);
+        case 2: return max_blocks_t<2, true>(pmax);
+        case 4: return max_blocks_t<4, true>(pmax);
+        case 8: return max_blocks_t<8, true>(pmax);
+        case 16: return max_blocks_t<16, true>(pmax);
+        case 32: return max_blocks_t<32, true>(pmax);
+        default: return 0;
+        }
+    }
     switch (R) {
-    case 1: return max_blocks_t<1>(pmax);
-    case 2: return max_blocks_t<2>(pmax);
-    case 4: return max_blocks_t<4>(pmax);
-    case 8: return max_blocks_t<8>(pmax);
-    case 16: return max_blocks_t<16>(pmax);
+    case 1: return max_blocks_t<1, false>(pmax);
+    case 2: return max_blocks_t<2, false>(pmax);
+    case 4: return max_blocks_t<4, false>(pmax);
+    case 8: return max_blocks_t<8, false>(pmax);
+    case 16: return max_blocks_t<16, false>(pmax);
     default: return 0;
     }
+}
+
+
+// --------------------------------------------------------------------------
+// H10: gradient through the optimal vertex.  At a certified vertex b_S =
+// X_{Z,S}^{-1} y_Z (the vertex form of Section 3.2), so for a loss L with
+// g = dL/db:  w = X_{Z,S}^{-T} g_S,  dL/dy_Z = w,  dL/dX_{Z,S} = -w b_S^T,
+// and every other entry of dL/dy and dL/dX is zero.  One wave per solve;
+// the dense zero fill dominates and streams at HBM write bandwidth.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_backward(BackwardArgs a)
+{
+    __shared__ float A[32 * ALD];
+    __shared__ int piv[32];
+    const int l = lane_id();
+    const int s = blockIdx.x;
+    if (s >= a.num_solves) return;
+    const int k = a.problem ? a.problem[s] : s;
+    const int64_t r0 = a.row_off[k];
+    const int n = (int)(a.row_off[k + 1] - r0);
+    const int p = a.p_arr[k];
+    const float *X = a.X + a.x_off[k];
+    float *gX = a.grad_X + a.x_off[k];
+    float *gy = a.grad_y + r0;
+    const int64_t o = (int64_t)s * a.path_len + a.step;
+    const float *b = a.b + (int64_t)a.path_len * a.b_off[s] + (int64_t)a.step * p;
+    const int status = a.status[o];
+    const float bl = (l < p) ? b[l] : 0.f;
+    const uint64_t sb = ballot(l < p && bl != 0.f);
+    int ns = popc64(sb);
+    const int zl = (l < ZPAD) ? a.zrows[(int64_t)ZPAD * o + l] : -1;
+    const int nz = popc64(ballot(l < ZPAD && zl >= 0));
+    bool ok = (status == ST_CERTIFIED) && ns == nz && ns > 0;
+    if (ok && l < ns && (zl < 0 || zl >= n)) ok = false;
+    ok = ballot(!ok) == 0;
+    // dense zeros
+    const int np = n * p;
+    for (int e = l; e < np; e += 64) gX[e] = 0.f;
+    for (int i = l; i < n; i += 64) gy[i] = 0.f;
+    if (!ok) return;
+    // S in ascending order, one column index per lane c < ns
+    int sc = -1;
+    if (l < p && bl != 0.f) sc = l;
+    const int cpos = mbcnt(sb); // position of lane l's column among S
+    __shared__ int sidx[32];
+    if (sc >= 0) sidx[cpos] = sc;
+    __syncthreads();
+    for (int q = 0; q < ns; ++q) {
+        const int zq = rdlane(zl, q);
+        if (l < ns) A[q * ALD + l] = X[(int64_t)zq * p + sidx[l]];
+    }
+    __syncthreads();
+    if (!lu_factor(A, piv, ns)) return;
+    const float g = (l < ns) ? a.grad_b[a.b_off[s] + sidx[l]] : 0.f;
+    const float w = lu_solve_t(A, piv, ns, g); // lane q: w_q
+    const float bS = (l < ns) ? b[sidx[l]] : 0.f;
+    // the zero fill must land before the non-zeros overwrite it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (l < ns) gy[zl] = w;
+    for (int c = 0; c < ns; ++c) {
+        const float bc = rdlane(bS, c);
+        if (l < ns) gX[(int64_t)zl * p + sidx[c]] = -w * bc;
+    }
+}
+
+hipError_t launch_backward(const BackwardArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_backward, dim3(a.num_solves), dim3(64), 0, s, a);
+    return hipGetLastError();
 }
 
 } // namespace ladl

@@ -39,63 +39,133 @@ constexpr int DPP_MIRROR = 0x140;  // row_mirror
 constexpr int DPP_SHR1 = 0x111, DPP_SHR2 = 0x112, DPP_SHR4 = 0x114, DPP_SHR8 = 0x118;
 constexpr int DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
 
-// Butterfly within each row of 16 lanes, then the four row results
-// combined through readlane: every lane returns the same value, and the
-// order of the additions is fixed.
+// Reductions: prefix combine within each row of 16 lanes (row shifts),
+// then across rows with the row broadcasts of lanes 15 and 31; lane 63 ends
+// with the result, which one readlane makes wave-uniform.  The order of the
+// operations is fixed, so results are deterministic.
 __device__ __forceinline__ float wsum(float v)
 {
-    v += dpp<DPP_XOR1>(0.f, v);
-    v += dpp<DPP_XOR2>(0.f, v);
-    v += dpp<DPP_HMIRROR>(0.f, v);
-    v += dpp<DPP_MIRROR>(0.f, v);
-    return (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
+    v += dpp<DPP_SHR1>(0.f, v);
+    v += dpp<DPP_SHR2>(0.f, v);
+    v += dpp<DPP_SHR4>(0.f, v);
+    v += dpp<DPP_SHR8>(0.f, v);
+    v += dpp<DPP_BCAST15, 0xA>(0.f, v);
+    v += dpp<DPP_BCAST31, 0xC>(0.f, v);
+    return rdlane(v, 63);
 }
 
-// three independent sums, interleaved for latency
+// two or three independent sums, interleaved for latency
+__device__ __forceinline__ void wsum2(float &a, float &b)
+{
+    a += dpp<DPP_SHR1>(0.f, a);
+    b += dpp<DPP_SHR1>(0.f, b);
+    a += dpp<DPP_SHR2>(0.f, a);
+    b += dpp<DPP_SHR2>(0.f, b);
+    a += dpp<DPP_SHR4>(0.f, a);
+    b += dpp<DPP_SHR4>(0.f, b);
+    a += dpp<DPP_SHR8>(0.f, a);
+    b += dpp<DPP_SHR8>(0.f, b);
+    a += dpp<DPP_BCAST15, 0xA>(0.f, a);
+    b += dpp<DPP_BCAST15, 0xA>(0.f, b);
+    a += dpp<DPP_BCAST31, 0xC>(0.f, a);
+    b += dpp<DPP_BCAST31, 0xC>(0.f, b);
+    a = rdlane(a, 63);
+    b = rdlane(b, 63);
+}
+
 __device__ __forceinline__ void wsum3(float &a, float &b, float &c)
 {
-    a += dpp<DPP_XOR1>(0.f, a);
-    b += dpp<DPP_XOR1>(0.f, b);
-    c += dpp<DPP_XOR1>(0.f, c);
-    a += dpp<DPP_XOR2>(0.f, a);
-    b += dpp<DPP_XOR2>(0.f, b);
-    c += dpp<DPP_XOR2>(0.f, c);
-    a += dpp<DPP_HMIRROR>(0.f, a);
-    b += dpp<DPP_HMIRROR>(0.f, b);
-    c += dpp<DPP_HMIRROR>(0.f, c);
-    a += dpp<DPP_MIRROR>(0.f, a);
-    b += dpp<DPP_MIRROR>(0.f, b);
-    c += dpp<DPP_MIRROR>(0.f, c);
-    a = (rdlane(a, 0) + rdlane(a, 16)) + (rdlane(a, 32) + rdlane(a, 48));
-    b = (rdlane(b, 0) + rdlane(b, 16)) + (rdlane(b, 32) + rdlane(b, 48));
-    c = (rdlane(c, 0) + rdlane(c, 16)) + (rdlane(c, 32) + rdlane(c, 48));
+    a += dpp<DPP_SHR1>(0.f, a);
+    b += dpp<DPP_SHR1>(0.f, b);
+    c += dpp<DPP_SHR1>(0.f, c);
+    a += dpp<DPP_SHR2>(0.f, a);
+    b += dpp<DPP_SHR2>(0.f, b);
+    c += dpp<DPP_SHR2>(0.f, c);
+    a += dpp<DPP_SHR4>(0.f, a);
+    b += dpp<DPP_SHR4>(0.f, b);
+    c += dpp<DPP_SHR4>(0.f, c);
+    a += dpp<DPP_SHR8>(0.f, a);
+    b += dpp<DPP_SHR8>(0.f, b);
+    c += dpp<DPP_SHR8>(0.f, c);
+    a += dpp<DPP_BCAST15, 0xA>(0.f, a);
+    b += dpp<DPP_BCAST15, 0xA>(0.f, b);
+    c += dpp<DPP_BCAST15, 0xA>(0.f, c);
+    a += dpp<DPP_BCAST31, 0xC>(0.f, a);
+    b += dpp<DPP_BCAST31, 0xC>(0.f, b);
+    c += dpp<DPP_BCAST31, 0xC>(0.f, c);
+    a = rdlane(a, 63);
+    b = rdlane(b, 63);
+    c = rdlane(c, 63);
+}
+
+// two sums and two minima in one interleaved pass
+__device__ __forceinline__ void wsum2_min2(float &a, float &b, float &c, float &d)
+{
+    const float I = __builtin_inff();
+    a += dpp<DPP_SHR1>(0.f, a);
+    b += dpp<DPP_SHR1>(0.f, b);
+    c = fminf(c, dpp<DPP_SHR1>(I, c));
+    d = fminf(d, dpp<DPP_SHR1>(I, d));
+    a += dpp<DPP_SHR2>(0.f, a);
+    b += dpp<DPP_SHR2>(0.f, b);
+    c = fminf(c, dpp<DPP_SHR2>(I, c));
+    d = fminf(d, dpp<DPP_SHR2>(I, d));
+    a += dpp<DPP_SHR4>(0.f, a);
+    b += dpp<DPP_SHR4>(0.f, b);
+    c = fminf(c, dpp<DPP_SHR4>(I, c));
+    d = fminf(d, dpp<DPP_SHR4>(I, d));
+    a += dpp<DPP_SHR8>(0.f, a);
+    b += dpp<DPP_SHR8>(0.f, b);
+    c = fminf(c, dpp<DPP_SHR8>(I, c));
+    d = fminf(d, dpp<DPP_SHR8>(I, d));
+    a += dpp<DPP_BCAST15, 0xA>(0.f, a);
+    b += dpp<DPP_BCAST15, 0xA>(0.f, b);
+    c = fminf(c, dpp<DPP_BCAST15, 0xA>(I, c));
+    d = fminf(d, dpp<DPP_BCAST15, 0xA>(I, d));
+    a += dpp<DPP_BCAST31, 0xC>(0.f, a);
+    b += dpp<DPP_BCAST31, 0xC>(0.f, b);
+    c = fminf(c, dpp<DPP_BCAST31, 0xC>(I, c));
+    d = fminf(d, dpp<DPP_BCAST31, 0xC>(I, d));
+    a = rdlane(a, 63);
+    b = rdlane(b, 63);
+    c = rdlane(c, 63);
+    d = rdlane(d, 63);
 }
 
 __device__ __forceinline__ float wmin(float v)
 {
-    v = fminf(v, dpp<DPP_XOR1>(v, v));
-    v = fminf(v, dpp<DPP_XOR2>(v, v));
-    v = fminf(v, dpp<DPP_HMIRROR>(v, v));
-    v = fminf(v, dpp<DPP_MIRROR>(v, v));
-    return fminf(fminf(rdlane(v, 0), rdlane(v, 16)), fminf(rdlane(v, 32), rdlane(v, 48)));
+    const float I = __builtin_inff();
+    v = fminf(v, dpp<DPP_SHR1>(I, v));
+    v = fminf(v, dpp<DPP_SHR2>(I, v));
+    v = fminf(v, dpp<DPP_SHR4>(I, v));
+    v = fminf(v, dpp<DPP_SHR8>(I, v));
+    v = fminf(v, dpp<DPP_BCAST15, 0xA>(I, v));
+    v = fminf(v, dpp<DPP_BCAST31, 0xC>(I, v));
+    return rdlane(v, 63);
 }
 
 __device__ __forceinline__ float wmax(float v)
 {
-    v = fmaxf(v, dpp<DPP_XOR1>(v, v));
-    v = fmaxf(v, dpp<DPP_XOR2>(v, v));
-    v = fmaxf(v, dpp<DPP_HMIRROR>(v, v));
-    v = fmaxf(v, dpp<DPP_MIRROR>(v, v));
-    return fmaxf(fmaxf(rdlane(v, 0), rdlane(v, 16)), fmaxf(rdlane(v, 32), rdlane(v, 48)));
+    const float I = -__builtin_inff();
+    v = fmaxf(v, dpp<DPP_SHR1>(I, v));
+    v = fmaxf(v, dpp<DPP_SHR2>(I, v));
+    v = fmaxf(v, dpp<DPP_SHR4>(I, v));
+    v = fmaxf(v, dpp<DPP_SHR8>(I, v));
+    v = fmaxf(v, dpp<DPP_BCAST15, 0xA>(I, v));
+    v = fmaxf(v, dpp<DPP_BCAST31, 0xC>(I, v));
+    return rdlane(v, 63);
 }
 
 __device__ __forceinline__ int wmin_i(int v)
 {
-    v = min(v, dppi<DPP_XOR1>(v, v));
-    v = min(v, dppi<DPP_XOR2>(v, v));
-    v = min(v, dppi<DPP_HMIRROR>(v, v));
-    v = min(v, dppi<DPP_MIRROR>(v, v));
-    return min(min(rdlane(v, 0), rdlane(v, 16)), min(rdlane(v, 32), rdlane(v, 48)));
+    const int I = 0x7fffffff;
+    v = min(v, dppi<DPP_SHR1>(I, v));
+    v = min(v, dppi<DPP_SHR2>(I, v));
+    v = min(v, dppi<DPP_SHR4>(I, v));
+    v = min(v, dppi<DPP_SHR8>(I, v));
+    v = min(v, dppi<DPP_BCAST15, 0xA>(I, v));
+    v = min(v, dppi<DPP_BCAST31, 0xC>(I, v));
+    return rdlane(v, 63);
 }
 
 // double-precision sum (used only by the optimality certificate)

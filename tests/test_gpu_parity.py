@@ -88,7 +88,7 @@ def _pack(blocks, lams):
 def test_edge_shapes(torch, kernel):
     rng = np.random.default_rng(3)
     blocks, lams = [], []
-    for n in [1, 2, 3, 5, 63, 64, 65, 127, 128, 129, 255, 257, 511, 513, 1000, 1024]:
+    for n in [1, 2, 3, 5, 63, 64, 65, 127, 128, 129, 255, 257, 511, 513, 1000, 1024, 1025, 1500, 2048]:
         for p in [1, 2, 5, 17, 32]:
             X = rng.standard_normal((n, p))
             y = X[:, : min(p, 3)] @ rng.uniform(-3, 3, min(p, 3)) + rng.laplace(0, 1, n)
