@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -91,6 +92,9 @@ struct ladl_graph_s {
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
 };
+
+static int layout_workspace(ladl_plan_t pl);
+static void set_schedule(ladl_plan_t pl, Bucket &b, bool xg);
 
 // exported functions: C linkage comes from their declarations in ladlasso.h
 
@@ -293,17 +297,12 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         for (int s : ids) b.pmax = std::max(b.pmax, (int)pl->p[pl->problem[s]]);
         b.count = (int)ids.size();
         order.insert(order.end(), ids.begin(), ids.end());
-        b.xg = R >= 32 || wave_lds_bytes(R, b.pmax, false) > LDS_RESIDENT_MAX;
-        size_t lds = wave_lds_bytes(R, b.pmax, b.xg);
+        const bool xg = R >= 32 || wave_lds_bytes(R, b.pmax, false) > LDS_RESIDENT_MAX;
+        size_t lds = wave_lds_bytes(R, b.pmax, xg);
         if (lds > h->lds_max)
             return bad(LADL_EUNSUPPORTED, "bucket R=%d p=%d needs %zu bytes of LDS (device limit %zu)", R, b.pmax,
                        lds, h->lds_max);
-        b.per_cu = std::max(1, wave_max_blocks_per_cu(R, b.pmax, b.xg));
-        b.grid = std::min<int64_t>(b.count, (int64_t)b.per_cu * h->num_cu);
-        if (b.xg) {
-            b.ws_off = pl->wws_floats;
-            pl->wws_floats += (int64_t)b.grid * (int64_t)wave_ws_floats_host(R, b.pmax);
-        }
+        set_schedule(pl, b, xg);
         pl->buckets.push_back(b);
     }
     // plain kernel: all solves, decreasing cost
@@ -320,11 +319,15 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         (e = upload(&pl->d_problem, pl->problem)) != hipSuccess || (e = upload(&pl->d_order, order)) != hipSuccess ||
         (e = upload(&pl->d_counters, zeros)) != hipSuccess ||
         (e = upload(&pl->d_order_plain, order_plain)) != hipSuccess ||
-        (e = upload(&pl->d_counter_plain, std::vector<int32_t>(1, 0))) != hipSuccess ||
-        (pl->wws_floats > 0 && (e = hipMalloc((void **)&pl->d_wws, sizeof(float) * (size_t)pl->wws_floats)) != hipSuccess)) {
+        (e = upload(&pl->d_counter_plain, std::vector<int32_t>(1, 0))) != hipSuccess) {
         plan_free_device(pl);
         delete pl;
         return hipfail(e, "plan upload");
+    }
+    if ((rc = layout_workspace(pl)) != LADL_OK) {
+        plan_free_device(pl);
+        delete pl;
+        return rc;
     }
     if (pl->buckets.size() > 1) {
         pl->bstreams.resize(pl->buckets.size(), nullptr);
@@ -408,6 +411,46 @@ static SolveArgs base_args(ladl_plan_t pl, const float *X, const float *y, const
     return a;
 }
 
+// workspace slices for the buckets whose X lives in HBM; grows the buffer
+static int layout_workspace(ladl_plan_t pl)
+{
+    int64_t tot = 0;
+    for (Bucket &b : pl->buckets) {
+        b.ws_off = tot;
+        if (b.xg) tot += (int64_t)b.grid * (int64_t)wave_ws_floats_host(b.R, b.pmax);
+    }
+    if (tot > pl->wws_floats || (tot > 0 && !pl->d_wws)) {
+        (void)hipFree(pl->d_wws);
+        pl->d_wws = nullptr;
+        hipError_t e = hipMalloc((void **)&pl->d_wws, sizeof(float) * (size_t)tot);
+        if (e != hipSuccess) return hipfail(e, "workspace");
+        pl->wws_floats = tot;
+    }
+    return LADL_OK;
+}
+
+static void set_schedule(ladl_plan_t pl, Bucket &b, bool xg)
+{
+    b.xg = xg;
+    b.per_cu = std::max(1, wave_max_blocks_per_cu(b.R, b.pmax, b.xg));
+    b.grid = (int)std::min<int64_t>(b.count, (int64_t)b.per_cu * pl->h->num_cu);
+}
+
+static hipError_t launch_bucket(ladl_plan_t pl, size_t bi, const SolveArgs &base, hipStream_t s)
+{
+    const Bucket &bk = pl->buckets[bi];
+    SolveArgs a = base;
+    a.order = pl->d_order + bk.offset;
+    a.num_items = bk.count;
+    a.counter = pl->d_counters + bi;
+    a.pmax = bk.pmax;
+    if (bk.xg) {
+        a.gws = pl->d_wws + bk.ws_off;
+        a.gws_stride = (int64_t)wave_ws_floats_host(bk.R, bk.pmax);
+    }
+    return launch_wave(bk.R, bk.xg, a, bk.grid, s);
+}
+
 static int enqueue_wave(ladl_plan_t pl, const float *X, const float *y, const float *lam, const float *b_init,
                         float *b, float *obj, uint32_t *active, int32_t *zr, int32_t *st, int32_t *it, int t0,
                         int t1, hipStream_t s)
@@ -420,16 +463,8 @@ static int enqueue_wave(ladl_plan_t pl, const float *X, const float *y, const fl
         const Bucket &bk = pl->buckets[bi];
         hipStream_t bs = fork ? pl->bstreams[bi] : s;
         if (fork && (e = hipStreamWaitEvent(bs, pl->ev_fork, 0)) != hipSuccess) return hipfail(e, "fork wait");
-        SolveArgs a = base_args(pl, X, y, lam, b_init, b, obj, active, zr, st, it, t0, t1);
-        a.order = pl->d_order + bk.offset;
-        a.num_items = bk.count;
-        a.counter = pl->d_counters + bi;
-        a.pmax = bk.pmax;
-        if (bk.xg) {
-            a.gws = pl->d_wws + bk.ws_off;
-            a.gws_stride = (int64_t)wave_ws_floats_host(bk.R, bk.pmax);
-        }
-        e = launch_wave(bk.R, bk.xg, a, bk.grid, bs);
+        (void)bk;
+        e = launch_bucket(pl, bi, base_args(pl, X, y, lam, b_init, b, obj, active, zr, st, it, t0, t1), bs);
         if (e != hipSuccess) return hipfail(e, "solve kernel launch");
         if (fork && (e = hipEventRecord(pl->ev_join[bi], bs)) != hipSuccess) return hipfail(e, "join event");
     }
@@ -563,11 +598,94 @@ int ladl_graph_destroy(ladl_graph_t g)
     return LADL_OK;
 }
 
+// Tuning cache: one line per decision, "<device name> <R> <pmax> <xg>", in
+// the file named by LADL_TUNE_CACHE (optional).
+static std::string device_name(int dev)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string n = prop.gcnArchName;
+    for (char &c : n)
+        if (c == ' ') c = '_';
+    return n;
+}
+
+static int cache_lookup(const std::string &dev, int R, int pmax)
+{
+    const char *path = std::getenv("LADL_TUNE_CACHE");
+    if (!path) return -1;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return -1;
+    char name[256];
+    int r, pm, xg, found = -1;
+    while (std::fscanf(f, "%255s %d %d %d", name, &r, &pm, &xg) == 4)
+        if (dev == name && r == R && pm == pmax) found = xg;
+    std::fclose(f);
+    return found;
+}
+
+static void cache_store(const std::string &dev, int R, int pmax, int xg)
+{
+    const char *path = std::getenv("LADL_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d\n", dev.c_str(), R, pmax, xg);
+    std::fclose(f);
+}
+
 int ladl_autotune(ladl_plan_t pl, const float *X, const float *y, const float *lam, float *b, float *obj,
                   uint32_t *active, int32_t *zr, int32_t *st, void *stream)
 {
-    if (!pl) return fail(LADL_EINVAL, "plan is NULL");
-    return LADL_OK;
+    int rc = check_solve_ptrs(pl, X, y, lam, b, obj, active, zr, st);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const std::string dev = device_name(pl->h->device);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hipfail(e, "tuning events");
+    }
+    for (size_t bi = 0; bi < pl->buckets.size() && rc == LADL_OK; ++bi) {
+        Bucket &bk = pl->buckets[bi];
+        const bool can_lds = bk.R < 32 && wave_lds_bytes(bk.R, bk.pmax, false) <= pl->h->lds_max;
+        if (!can_lds) continue; // only the workspace schedule exists
+        int cached = cache_lookup(dev, bk.R, bk.pmax);
+        if (cached >= 0) {
+            set_schedule(pl, bk, cached != 0);
+            continue;
+        }
+        float best_ms = 1e30f;
+        bool best_xg = bk.xg;
+        for (int xg = 0; xg < 2 && rc == LADL_OK; ++xg) {
+            set_schedule(pl, bk, xg != 0);
+            if ((rc = layout_workspace(pl)) != LADL_OK) break;
+            SolveArgs a = base_args(pl, X, y, lam, nullptr, b, obj, active, zr, st, nullptr, 0, pl->L);
+            float ms = 0.f;
+            for (int rep = 0; rep < 2; ++rep) { // first run warms up
+                if ((e = launch_reset(pl->d_counters, (int)pl->buckets.size(), s)) != hipSuccess ||
+                    (e = hipEventRecord(e0, s)) != hipSuccess || (e = launch_bucket(pl, bi, a, s)) != hipSuccess ||
+                    (e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+                    (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+                    rc = hipfail(e, "tuning run");
+                    break;
+                }
+            }
+            if (rc == LADL_OK && ms < best_ms) {
+                best_ms = ms;
+                best_xg = xg != 0;
+            }
+        }
+        if (rc == LADL_OK) {
+            set_schedule(pl, bk, best_xg);
+            cache_store(dev, bk.R, bk.pmax, best_xg ? 1 : 0);
+        }
+    }
+    if (rc == LADL_OK) rc = layout_workspace(pl);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int ladl_plan_describe(ladl_plan_t pl, char *buf, int64_t len)

@@ -173,3 +173,22 @@ def test_c1_full_size_sampled(torch):
     print(st, flush=True)
     assert not fails, fails[:5]
     assert np.all(np.isin(g["status"], [L.CERTIFIED, L.NONUNIQUE]))
+
+
+def test_autotune_then_solve(torch, tmp_path, monkeypatch):
+    """The autotuner times both X placements per bucket on the caller's data,
+    caches its choice, and the tuned plan keeps parity."""
+    monkeypatch.setenv("LADL_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    w = W.config2(num_subsets=96)
+    plan = L.Plan.for_workload(w)
+    d = L.to_device(w)
+    out = plan.alloc_outputs()
+    plan.autotune(d["X"], d["y"], d["lam"], out)
+    print(plan.describe(), flush=True)
+    out = plan.solve(d["X"], d["y"], d["lam"])
+    torch.cuda.synchronize()
+    assert_parity(w, to_numpy(out), oracle_ref(w))
+    assert (tmp_path / "tune.txt").exists()
+    plan2 = L.Plan.for_workload(w)          # second plan reads the cache
+    plan2.autotune(d["X"], d["y"], d["lam"], plan2.alloc_outputs())
+    assert plan2.describe() == plan.describe()
