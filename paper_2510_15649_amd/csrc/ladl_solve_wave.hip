@@ -249,10 +249,9 @@ LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&wt)[R], 
     for (int it = 0; it < 3; ++it) {
         float m = FINF;
 #pragma unroll
-        for (int k = 0; k < R; ++k)
-            if (a[k] > lo) m = fminf(m, a[k]);
-        if (av > lo) m = fminf(m, av);
-        m = wmin(m);
+        for (int k = 0; k < R; ++k) m = (a[k] > lo && a[k] < m) ? a[k] : m;
+        m = (av > lo && av < m) ? av : m;
+        m = wmin_nn(m);
         if (m == FINF) {
             if (lo < 0.f) return Sel{FINF, 0, -1, false}; // no candidate at all
             return owner_of<R, XG>(a, av, lo);                 // weight exhausted by rounding
@@ -391,35 +390,21 @@ template <int R, bool XG>
 LADL_INL bool coord_update(Wave<R, XG> &w, float (&r)[R], float &bv, int j, const float (&x)[R])
 {
     const int l = lane_id();
-    float a[R];
-    uint32_t negb = 0;
+    // pass 1: weight of the kinks below and at the current b_j (signs only)
     float bel = 0.f, at = 0.f;
-    float umin = FINF, uw = 0.f, dmin = FINF, dw = 0.f;
-    int uk = 0, dk = 0;
-    bool utie = false, dtie = false;
+    uint32_t negb = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const float rr = r[k], ax = fabsf(x[k]);
         const bool z = (rr == 0.f);
         const bool neg = (fbits(rr) ^ fbits(x[k])) < 0;
-        const float ak = (z || ax == 0.f) ? FINF : fabsf(rr) * __builtin_amdgcn_rcpf(ax);
-        a[k] = ak;
-        negb |= neg ? (1u << k) : 0u;
-        at += z ? ax : 0.f;
-        bel += (!z && neg) ? ax : 0.f;
-        const bool dn = neg && ak < dmin, up = !neg && ak < umin;
-        dtie = dtie || (neg && ak == dmin && ak < FINF);
-        utie = utie || (!neg && ak == umin && ak < FINF);
-        dmin = dn ? ak : dmin;
-        dw = dn ? ax : dw;
-        dk = dn ? k : dk;
-        umin = up ? ak : umin;
-        uw = up ? ax : uw;
-        uk = up ? k : uk;
+        const float wz = z ? ax : 0.f;
+        at += wz;
+        bel += neg ? ax - wz : 0.f;
+        negb |= (uint32_t)neg << k;
     }
     const float bj = rdlane(bv, j);
-    float dminw = dmin, uminw = umin;
-    wsum2_min2(bel, at, dminw, uminw);
+    wsum2(bel, at);
     const float lam = w.lam;
     const float W = rdlane(w.cav, j) + lam;
     if (!(W > 0.f)) return false;
@@ -435,29 +420,32 @@ LADL_INL bool coord_update(Wave<R, XG> &w, float (&r)[R], float &bv, int j, cons
         return false; // b_j is already the minimiser
     const float T = down ? (belT - half) : (half - belT - atT);
     auto reached = [&](float c) { return down ? (c > T) : (c >= T); };
-    const float smin = down ? dmin : umin;
-    const float sw_ = down ? dw : uw;
-    const int sk = down ? dk : uk;
-    const bool stie = down ? dtie : utie;
+    // pass 2: the kinks on the moving side, as distances from b_j, and each
+    // lane's nearest one with the weight of all its kinks at that distance
+    const uint32_t dmask = down ? 0xFFFFFFFFu : 0u;
+    float a[R];
+    float smin = FINF, sw = 0.f;
+    int sk = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const float ax = fabsf(x[k]);
+        const bool side = ((negb ^ dmask) >> k) & 1u ? false : true;
+        const bool valid = side && r[k] != 0.f && ax != 0.f;
+        const float ak = valid ? fabsf(r[k]) * __builtin_amdgcn_rcpf(ax) : FINF;
+        a[k] = ak;
+        const bool lt = ak < smin, eq = ak == smin;
+        sw = lt ? ax : (eq ? sw + ax : sw);
+        sk = lt ? k : sk;
+        smin = lt ? ak : smin;
+    }
     const bool lcand = (lam > 0.f) && (down ? (bj > 0.f) : (bj < 0.f));
     const float al = fabsf(bj);
-    const float m1 = down ? dminw : uminw;
+    const float m1 = wmin_nn(smin);
     if (!(m1 < FINF) && !lcand) return false;
     const float mm = lcand ? fminf(m1, al) : m1;
     // weight of the nearest kink(s)
     const uint64_t ob = ballot(smin == mm);
-    float wm;
-    if (popc64(ob) > 1 || ballot(stie && smin == mm)) {
-        float part = 0.f;
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const bool side = (((negb >> k) & 1u) != 0u) == down;
-            part += (side && a[k] == mm) ? fabsf(x[k]) : 0.f;
-        }
-        wm = wsum(part);
-    } else {
-        wm = ob ? rdlane(sw_, first_lane(ob)) : 0.f;
-    }
+    float wm = (popc64(ob) > 1) ? wsum((smin == mm) ? sw : 0.f) : (ob ? rdlane(sw, first_lane(ob)) : 0.f);
     if (lcand && al == mm) wm += lam;
     float nb;
     int olane = -1, oslot = -1;
@@ -470,16 +458,12 @@ LADL_INL bool coord_update(Wave<R, XG> &w, float (&r)[R], float &bv, int j, cons
         }
         nb = virt ? 0.f : (down ? bj - mm : bj + mm);
     } else {
-        float ac[R], wt[R];
+        float wt[R];
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const bool side = (((negb >> k) & 1u) != 0u) == down;
-            ac[k] = side ? a[k] : FINF;
-            wt[k] = side ? fabsf(x[k]) : 0.f;
-        }
+        for (int k = 0; k < R; ++k) wt[k] = (a[k] < FINF) ? fabsf(x[k]) : 0.f;
         const float av = (l == 0 && lcand) ? al : FINF;
         const float wv = (l == 0 && lcand) ? lam : 0.f;
-        Sel sl = wselect<R, XG>(w, ac, wt, av, wv, T, down, mm, wm);
+        Sel sl = wselect<R, XG>(w, a, wt, av, wv, T, down, mm, wm);
         if (!(sl.a < FINF)) return false;
         virt = sl.virt;
         olane = sl.lane;
@@ -488,12 +472,11 @@ LADL_INL bool coord_update(Wave<R, XG> &w, float (&r)[R], float &bv, int j, cons
     }
     const float d = nb - bj;
     if (d == 0.f || !__builtin_isfinite(d)) return false;
+    const bool own = !virt && l == olane;
 #pragma unroll
-    for (int k = 0; k < R; ++k) r[k] = fmaf(-x[k], d, r[k]);
-    if (!virt && l == olane) {
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-            if (k == oslot) r[k] = 0.f; // the median row is now on its hyperplane
+    for (int k = 0; k < R; ++k) {
+        const float rn = fmaf(-x[k], d, r[k]);
+        r[k] = (own && k == oslot) ? 0.f : rn; // the median row is now on its hyperplane
     }
     bv = (l == j) ? nb : bv;
     return true;

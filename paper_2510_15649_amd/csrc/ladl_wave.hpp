@@ -168,6 +168,22 @@ __device__ __forceinline__ int wmin_i(int v)
     return rdlane(v, 63);
 }
 
+// Minimum of non-negative floats (or +inf): for such values the bit
+// patterns order like unsigned integers, so the minimum is ~max(~bits).  The
+// unsigned max has identity 0, which is what DPP writes into lanes whose
+// source lies outside the row, so every row step is one v_max_u32 with DPP.
+__device__ __forceinline__ float wmin_nn(float v)
+{
+    uint32_t u = ~(uint32_t)fbits(v);
+    u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, DPP_SHR1, 0xF, 0xF, true));
+    u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, DPP_SHR2, 0xF, 0xF, true));
+    u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, DPP_SHR4, 0xF, 0xF, true));
+    u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, DPP_SHR8, 0xF, 0xF, true));
+    u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, DPP_BCAST15, 0xA, 0xF, false));
+    u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, DPP_BCAST31, 0xC, 0xF, false));
+    return bitsf((int)~(uint32_t)__builtin_amdgcn_readlane((int)u, 63));
+}
+
 // double-precision sum (used only by the optimality certificate)
 __device__ __forceinline__ double wsum_d(double v)
 {
