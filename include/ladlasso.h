@@ -110,6 +110,11 @@ typedef struct {
     int32_t num_solves;
     const int32_t *problem; /* host [num_solves] or NULL: solve s uses problem s       */
     int32_t path_len;       /* >= 1                                                    */
+    const float *lambda_hint; /* host [num_solves * path_len] or NULL: the lambda values
+                                 the plan will mostly be run with; used only to order
+                                 the work queue (among solves of equal n*p, smaller
+                                 lambda first: those take longer), never read on the
+                                 device and not required to match later calls       */
 } ladl_layout;
 
 typedef struct ladl_handle_s *ladl_handle_t;
@@ -125,7 +130,8 @@ void ladl_default_options(ladl_options *opt);
 /*
  * Validate a layout and build a plan: per-solve metadata uploaded to the
  * device, solves bucketed by rows per lane and sorted by decreasing cost
- * (n_k * p_k) for the persistent work queue, and the schedule chosen.
+ * (n_k * p_k, then increasing lambda when lambda_hint is given) for the
+ * persistent work queue, and the schedule chosen.
  * Synchronous.  The plan keeps its own copies; layout arrays may be freed.
  */
 int ladl_plan_create(ladl_handle_t handle, const ladl_layout *layout, const ladl_options *opt,

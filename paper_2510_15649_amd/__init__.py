@@ -44,7 +44,8 @@ class Layout(C.Structure):
     _fields_ = [("num_problems", C.c_int32), ("row_off", C.POINTER(C.c_int64)),
                 ("x_off", C.POINTER(C.c_int64)), ("p", C.POINTER(C.c_int32)), ("p_uniform", C.c_int32),
                 ("x_len", C.c_int64), ("y_len", C.c_int64), ("num_solves", C.c_int32),
-                ("problem", C.POINTER(C.c_int32)), ("path_len", C.c_int32)]
+                ("problem", C.POINTER(C.c_int32)), ("path_len", C.c_int32),
+                ("lambda_hint", C.POINTER(C.c_float))]
 
 
 class LadlError(RuntimeError):
@@ -163,7 +164,7 @@ class Plan:
     """
 
     def __init__(self, row_off, p, *, x_len: int, y_len: int, problem=None, path_len: int = 1, x_off=None,
-                 options: Optional[Options] = None, handle: Optional[Handle] = None, **opt_kw):
+                 lambda_hint=None, options: Optional[Options] = None, handle: Optional[Handle] = None, **opt_kw):
         self.handle = handle or default_handle()
         self.options = options if options is not None else default_options(**opt_kw)
         self._row_off = np.ascontiguousarray(row_off, dtype=np.int64)
@@ -190,6 +191,12 @@ class Plan:
         lay.num_solves = S
         lay.problem = None if self._problem is None else self._problem.ctypes.data_as(C.POINTER(C.c_int32))
         lay.path_len = int(path_len)
+        self._lambda_hint = None
+        if lambda_hint is not None:
+            self._lambda_hint = np.ascontiguousarray(lambda_hint, dtype=np.float32)
+            if self._lambda_hint.size != S * int(path_len):
+                raise ValueError(f"lambda_hint has {self._lambda_hint.size} values, expected {S * int(path_len)}")
+            lay.lambda_hint = self._lambda_hint.ctypes.data_as(C.POINTER(C.c_float))
         h = C.c_void_p()
         check(lib().ladl_plan_create(self.handle.ptr, C.byref(lay), C.byref(self.options), C.byref(h)))
         self._plan = h
@@ -204,7 +211,7 @@ class Plan:
     @classmethod
     def for_workload(cls, w, **kw) -> "Plan":
         return cls(w.row_off, w.p, x_off=w.x_off, problem=w.problem, path_len=w.path_len,
-                   x_len=w.X.size, y_len=w.y.size, **kw)
+                   x_len=w.X.size, y_len=w.y.size, lambda_hint=w.lam, **kw)
 
     def __del__(self):
         if getattr(self, "_plan", None) and _lib is not None:

@@ -273,6 +273,19 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         acc += pl->p[pl->problem[s]];
     }
     pl->b_len = acc * L;
+    // queue order: decreasing n*p, then (with a lambda hint) increasing sum
+    // of the path's lambdas, since small-lambda solves run the longest
+    std::vector<double> lsum(S, 0.0);
+    if (lay->lambda_hint)
+        for (int s = 0; s < S; ++s)
+            for (int t = 0; t < L; ++t) lsum[s] += (double)lay->lambda_hint[(int64_t)s * L + t];
+    auto cost_gt = [&](int a, int c) {
+        int ka = pl->problem[a], kc = pl->problem[c];
+        int64_t ca = (pl->row_off[ka + 1] - pl->row_off[ka]) * pl->p[ka];
+        int64_t cc = (pl->row_off[kc + 1] - pl->row_off[kc]) * pl->p[kc];
+        if (ca != cc) return ca > cc;
+        return lsum[a] < lsum[c];
+    };
     // buckets by rows per lane; decreasing cost inside a bucket
     std::vector<int> Rs = {32, 16, 8, 4, 2, 1};
     std::vector<int32_t> order;
@@ -288,12 +301,7 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
             if (rows_per_lane(n) == R) ids.push_back(s);
         }
         if (ids.empty()) continue;
-        std::stable_sort(ids.begin(), ids.end(), [&](int a, int c) {
-            int ka = pl->problem[a], kc = pl->problem[c];
-            int64_t ca = (pl->row_off[ka + 1] - pl->row_off[ka]) * pl->p[ka];
-            int64_t cc = (pl->row_off[kc + 1] - pl->row_off[kc]) * pl->p[kc];
-            return ca > cc;
-        });
+        std::stable_sort(ids.begin(), ids.end(), cost_gt);
         for (int s : ids) b.pmax = std::max(b.pmax, (int)pl->p[pl->problem[s]]);
         b.count = (int)ids.size();
         order.insert(order.end(), ids.begin(), ids.end());
@@ -308,10 +316,7 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
     // plain kernel: all solves, decreasing cost
     std::vector<int32_t> order_plain(S);
     std::iota(order_plain.begin(), order_plain.end(), 0);
-    std::stable_sort(order_plain.begin(), order_plain.end(), [&](int a, int c) {
-        int ka = pl->problem[a], kc = pl->problem[c];
-        return (pl->row_off[ka + 1] - pl->row_off[ka]) * pl->p[ka] > (pl->row_off[kc + 1] - pl->row_off[kc]) * pl->p[kc];
-    });
+    std::stable_sort(order_plain.begin(), order_plain.end(), cost_gt);
     hipError_t e;
     std::vector<int32_t> zeros(pl->buckets.size() + 1, 0);
     if ((e = upload(&pl->d_row_off, pl->row_off)) != hipSuccess || (e = upload(&pl->d_x_off, pl->x_off)) != hipSuccess ||

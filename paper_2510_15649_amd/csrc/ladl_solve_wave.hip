@@ -17,7 +17,8 @@
 //   Xs  p columns of LDN = 64R+1 floats; row i of column j at j*LDN + i,
 //       row i owned by lane i%64, register slot i/64 (rows >= n are 0)
 //   ys, rn   y and the row norms ||x_i||_2, LDN each
-//   A   vertex matrix / LU factors, 32 x 33
+//   A   vertex matrix / LU factors, pmax rows of 33
+//   A0  the vertex matrix unfactored (refinement residuals), pmax x (pmax+1)
 //   small vectors of 32 (b, best b, column |x| sums, direction, scratch)
 //   gd  32 doubles (certificate), sa/sw 64+64 (selection compaction)
 #include "ladl_common.hpp"
@@ -34,11 +35,11 @@ __device__ __forceinline__ float unif(float v) { return bitsf(__builtin_amdgcn_r
 __host__ __device__ constexpr int wave_ldn(int R) { return 64 * R + 1; }
 
 // LDS floats per wave: gd, [Xs, ys, rn when resident], best residuals,
-// A (pmax rows), 6 vectors, sa/sw, zs/ss/piv
+// A (pmax rows), A0, 6 vectors, sa/sw, zs/ss/piv
 __host__ __device__ constexpr size_t wave_lds_floats(int R, int pmax, bool xg)
 {
-    return 64 + (xg ? 0 : (size_t)(pmax + 2) * wave_ldn(R)) + 64 * (size_t)R + (size_t)pmax * ALD + 6 * 32 + 128 +
-           3 * 32;
+    return 64 + (xg ? 0 : (size_t)(pmax + 2) * wave_ldn(R)) + 64 * (size_t)R + (size_t)pmax * ALD +
+           (size_t)pmax * (pmax + 1) + 6 * 32 + 128 + 3 * 32;
 }
 // global workspace floats per wave when X is not LDS-resident: Xs, ys, rn
 __host__ __device__ constexpr size_t wave_ws_floats(int R, int pmax) { return (size_t)(pmax + 2) * wave_ldn(R); }
@@ -47,10 +48,10 @@ template <int R, bool XG>
 struct Wave {
     static constexpr int LDN = wave_ldn(R);
     // Xs, ys, rn: LDS (XG false) or this wave's slice of a global workspace
-    float *Xs, *ys, *rn, *rbuf, *A, *vb, *vbb, *vca, *vd, *vg, *vt, *sa, *sw;
+    float *Xs, *ys, *rn, *rbuf, *A, *A0, *vb, *vbb, *vca, *vd, *vg, *vt, *sa, *sw;
     double *gd;
     int *zs, *ss, *piv;
-    int n, p, nslot;
+    int n, p, nslot, a0ld;
     float lam, ynorm1;
     float cav; // lane j: sum_i |x_ij|
     DevOpt opt;
@@ -76,6 +77,9 @@ LADL_INL void carve(Wave<R, XG> &w, float *smem, int pmax, float *ws)
     q += 64 * R;
     w.A = q;
     q += pmax * ALD;
+    w.A0 = q; // unfactored copy of the vertex matrix, row stride pmax + 1
+    w.a0ld = pmax + 1;
+    q += pmax * (pmax + 1);
     w.vb = q;
     q += 32;
     w.vbb = q;
@@ -119,7 +123,9 @@ template <int R, bool XG>
 LADL_INL bool load_problem(Wave<R, XG> &w, const float *__restrict__ X, const float *__restrict__ y)
 {
     constexpr int LDN = Wave<R, XG>::LDN;
-    const int l = lane_id(), n = w.n, p = w.p, top = 64 * w.nslot;
+    // rows n .. 64R-1 are zero padding (so hot loops read all R slots
+    // without guards: a zero row has a zero residual and no weight)
+    const int l = lane_id(), n = w.n, p = w.p, top = 64 * R;
     for (int j = 0; j < p; ++j)
         for (int i = n + l; i < top; i += 64) w.Xs[j * LDN + i] = 0.f;
     for (int i = n + l; i < top; i += 64) {
@@ -493,7 +499,7 @@ LADL_INL float ccd(Wave<R, XG> &w, float (&r)[R], float &bv, int frozen, float f
     int j = (frozen == 0) ? 1 : 0;
     float x[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) x[k] = (k < w.nslot) ? w.Xs[j * LDN + 64 * k + l] : 0.f;
+    for (int k = 0; k < R; ++k) x[k] = w.Xs[j * LDN + 64 * k + l];
     for (int sw = 0; sw < w.opt.max_sweeps; ++sw) {
         bool changed = false;
         for (int u = 0; u < p; ++u) {
@@ -503,7 +509,7 @@ LADL_INL float ccd(Wave<R, XG> &w, float (&r)[R], float &bv, int frozen, float f
             if (jn >= p) jn = (frozen == 0) ? 1 : 0;
             float xn[R];
 #pragma unroll
-            for (int k = 0; k < R; ++k) xn[k] = (k < w.nslot) ? w.Xs[jn * LDN + 64 * k + l] : 0.f;
+            for (int k = 0; k < R; ++k) xn[k] = w.Xs[jn * LDN + 64 * k + l];
             changed |= coord_update<R, XG>(w, r, bv, u, x);
             w.c_updates++;
 #pragma unroll
@@ -628,8 +634,9 @@ LADL_INL bool lu_factor(float *A, int *piv, int s)
 LADL_INL float lu_solve(const float *A, const int *piv, int s, float v)
 {
     const int l = lane_id();
+    const int pr = (l < s) ? piv[l] : 0; // lane k: row swapped with k
     for (int k = 0; k < s; ++k) {
-        int pk = uni(piv[k]);
+        int pk = rdlane(pr, k);
         if (pk != k) {
             float a = rdlane(v, k), b = rdlane(v, pk);
             v = (l == k) ? b : ((l == pk) ? a : v);
@@ -651,6 +658,7 @@ LADL_INL float lu_solve(const float *A, const int *piv, int s, float v)
 LADL_INL float lu_solve_t(const float *A, const int *piv, int s, float v)
 {
     const int l = lane_id();
+    const int pr = (l < s) ? piv[l] : 0;
     for (int c = 0; c < s; ++c) {
         if (l == c) v = v / A[c * ALD + c];
         float vc = rdlane(v, c);
@@ -661,7 +669,7 @@ LADL_INL float lu_solve_t(const float *A, const int *piv, int s, float v)
         if (l < c) v = fmaf(-A[c * ALD + l], vc, v);
     }
     for (int k = s - 1; k >= 0; --k) {
-        int pk = uni(piv[k]);
+        int pk = rdlane(pr, k);
         if (pk != k) {
             float a = rdlane(v, k), b = rdlane(v, pk);
             v = (l == k) ? b : ((l == pk) ? a : v);
@@ -670,30 +678,43 @@ LADL_INL float lu_solve_t(const float *A, const int *piv, int s, float v)
     return v;
 }
 
-// Vertex (zs, ss, s): A = X_{Z,S} factored in LDS, b_S = A^{-1} y_Z with
-// one refinement step (residual in fp64), b into vt, residuals into rv
-// (exact zeros on Z), objective into f.  Lane c returns b_{S_c} in bS.
+// Vertex (zs, ss, s): A = X_{Z,S} factored in LDS (A0 keeps it unfactored),
+// b_S = A^{-1} y_Z with up to three refinement steps (residual in fp64), b
+// into vt, residuals into rv (exact zeros on Z), objective into f.
 template <int R, bool XG>
 LADL_INL bool vertex_eval(Wave<R, XG> &w, float (&rv)[R], uint32_t zbits, int s, float &f)
 {
     constexpr int LDN = Wave<R, XG>::LDN;
-    const int l = lane_id();
-    for (int q = 0; q < s; ++q) {
-        int zq = uni(w.zs[q]);
-        if (l < s) w.A[q * ALD + l] = w.Xs[w.ss[l] * LDN + zq];
+    const int l = lane_id(), a0ld = w.a0ld;
+    // lane q < s: row Z_q and column S_q, held in registers so that the
+    // gathers below issue independent loads
+    const int zl = (l < s) ? w.zs[l] : 0;
+    const int jl = (l < s) ? w.ss[l] : 0;
+    // lane c gathers column S_c: A[q][c] = x_{Z_q, S_c}, four rows at a time
+    for (int q0 = 0; q0 < s; q0 += 4) {
+        float v[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int zq = rdlane(zl, q0 + t);
+            v[t] = (l < s && q0 + t < s) ? w.Xs[jl * LDN + zq] : 0.f;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (l < s && q0 + t < s) {
+                w.A[(q0 + t) * ALD + l] = v[t];
+                w.A0[(q0 + t) * a0ld + l] = v[t];
+            }
     }
     __syncthreads();
     if (!lu_factor(w.A, w.piv, s)) return false;
-    const int zl = (l < s) ? w.zs[l] : 0;
     const float yz = (l < s) ? w.ys[zl] : 0.f;
     float xs = lu_solve(w.A, w.piv, s, yz);
     // mixed-precision refinement: residual y_Z - X_{Z,S} b_S in fp64
     for (int it = 0; it < 3; ++it) {
         double acc = (double)yz;
         for (int c = 0; c < s; ++c) {
-            float xc = rdlane(xs, c);
-            int jc = uni(w.ss[c]);
-            if (l < s) acc -= (double)w.Xs[jc * LDN + zl] * (double)xc;
+            const float xc = rdlane(xs, c);
+            if (l < s) acc -= (double)w.A0[l * a0ld + c] * (double)xc;
         }
         const float corr = lu_solve(w.A, w.piv, s, (l < s) ? (float)acc : 0.f);
         xs += corr;
@@ -702,16 +723,15 @@ LADL_INL bool vertex_eval(Wave<R, XG> &w, float (&rv)[R], uint32_t zbits, int s,
     if (ballot(l < s && !__builtin_isfinite(xs))) return false;
     if (l < w.p) w.vt[l] = 0.f;
     __syncthreads();
-    if (l < s) w.vt[w.ss[l]] = xs;
+    if (l < s) w.vt[jl] = xs;
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < R; ++k) rv[k] = (k < w.nslot) ? w.ys[64 * k + l] : 0.f;
+    for (int k = 0; k < R; ++k) rv[k] = w.ys[64 * k + l];
     for (int c = 0; c < s; ++c) {
-        int jc = uni(w.ss[c]);
-        float bc = rdlane(xs, c);
+        const int jc = rdlane(jl, c);
+        const float bc = rdlane(xs, c);
 #pragma unroll
-        for (int k = 0; k < R; ++k)
-            if (k < w.nslot) rv[k] = fmaf(-w.Xs[jc * LDN + 64 * k + l], bc, rv[k]);
+        for (int k = 0; k < R; ++k) rv[k] = fmaf(-w.Xs[jc * LDN + 64 * k + l], bc, rv[k]);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k)
@@ -720,49 +740,48 @@ LADL_INL bool vertex_eval(Wave<R, XG> &w, float (&rv)[R], uint32_t zbits, int s,
     return true;
 }
 
-// LP optimality certificate at the evaluated vertex (A holds its LU):
-// u_i = sign(r_i) off Z, X_{Z,S}^T u_Z = lambda sign(b_S) - X_{Zc,S}^T u_Zc,
-// c = X^T u.  Lane q returns u_{Z_q} in u, lane j returns c_j in c.
+// LP optimality certificate at the evaluated vertex (A holds its LU, A0 the
+// matrix): u_i = sign(r_i) off Z, X_{Z,S}^T u_Z = lambda sign(b_S) -
+// X_{Zc,S}^T u_Zc, c = X^T u.  Lane q returns u_{Z_q} in u, lane j returns
+// c_j in c.
 template <int R, bool XG>
 LADL_INL bool certificate(Wave<R, XG> &w, const float (&rv)[R], uint32_t zbits, int s, float &u, float &c,
                             bool &unique)
 {
     constexpr int LDN = Wave<R, XG>::LDN;
-    const int l = lane_id(), p = w.p;
+    const int l = lane_id(), p = w.p, a0ld = w.a0ld;
+    const int zl = (l < s) ? w.zs[l] : 0;
+    const int jl = (l < s) ? w.ss[l] : 0;
+    // g_j = sum_i x_ij sign(r_i) in fp64 (rows of Z have r = 0); lane j
+    // keeps g_j
     double g = 0.0;
     for (int j = 0; j < p; ++j) {
         double part = 0.0;
 #pragma unroll
-        for (int k = 0; k < R; ++k)
-            if (k < w.nslot) part += (double)w.Xs[j * LDN + 64 * k + l] * (double)sgnf(rv[k]);
-        double gj = wsum_d(part);
-        if (l == j) g = gj;
+        for (int k = 0; k < R; ++k) part += (double)(w.Xs[j * LDN + 64 * k + l] * sgnf(rv[k]));
+        const double gj = wsum_d(part);
+        g = (l == j) ? gj : g;
     }
     if (l < p) w.gd[l] = g;
     __syncthreads();
     uint32_t smask = 0;
-    for (int q = 0; q < s; ++q) smask |= 1u << uni(w.ss[q]);
+    for (int q = 0; q < s; ++q) smask |= 1u << rdlane(jl, q);
     double rhs = 0.0;
-    int jq = 0;
-    if (l < s) {
-        jq = w.ss[l];
-        rhs = (double)w.lam * (double)sgnf(w.vt[jq]) - w.gd[jq];
-    }
+    if (l < s) rhs = (double)w.lam * (double)sgnf(w.vt[jl]) - w.gd[jl];
     u = lu_solve_t(w.A, w.piv, s, (float)rhs);
     // refinement: residual rhs - X_{Z,S}^T u in fp64
     for (int it = 0; it < 2; ++it) {
         double acc = rhs;
         for (int q = 0; q < s; ++q) {
-            float uq = rdlane(u, q);
-            int zq = uni(w.zs[q]);
-            if (l < s) acc -= (double)w.Xs[jq * LDN + zq] * (double)uq;
+            const float uq = rdlane(u, q);
+            if (l < s) acc -= (double)w.A0[q * a0ld + l] * (double)uq;
         }
         u += lu_solve_t(w.A, w.piv, s, (l < s) ? (float)acc : 0.f);
     }
     double cj = g;
     for (int q = 0; q < s; ++q) {
-        float uq = rdlane(u, q);
-        int zq = uni(w.zs[q]);
+        const float uq = rdlane(u, q);
+        const int zq = rdlane(zl, q);
         if (l < p) cj += (double)w.Xs[l * LDN + zq] * (double)uq;
     }
     c = (float)cj;
@@ -800,8 +819,10 @@ LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, f
         if (!vertex_eval<R, XG>(w, rv, zbits, s, f)) return ST_NOTCERT;
         if (certificate<R, XG>(w, rv, zbits, s, u, c, unique)) return unique ? ST_CERTIFIED : ST_NONUNIQUE;
         if (it >= maxp) return ST_MAXITER;
+        const int zl = (l < s) ? w.zs[l] : 0;
+        const int jl = (l < s) ? w.ss[l] : 0;
         uint32_t smask = 0;
-        for (int q = 0; q < s; ++q) smask |= 1u << uni(w.ss[q]);
+        for (int q = 0; q < s; ++q) smask |= 1u << rdlane(jl, q);
         const bool offS = (l < p) && !((smask >> l) & 1u);
         const float colabs = (l < p) ? w.vca[l] : 0.f;
         float vr = (l < s && 1.f - fabsf(u) < -TOL_U) ? 1.f - fabsf(u) : FINF;
@@ -817,30 +838,29 @@ LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, f
             rhs = (l == sel) ? -sgnf(usel) : 0.f;
         } else {
             dj0 = sgnf(rdlane(c, sel));
-            rhs = (l < s) ? -w.Xs[sel * LDN + w.zs[l]] * dj0 : 0.f;
+            rhs = (l < s) ? -w.Xs[sel * LDN + zl] * dj0 : 0.f;
         }
         const float dS = lu_solve(w.A, w.piv, s, rhs);
         if (l < p) w.vd[l] = 0.f;
         __syncthreads();
-        if (l < s) w.vd[w.ss[l]] = dS;
+        if (l < s) w.vd[jl] = dS;
         if (!type1 && l == 0) w.vd[sel] = dj0;
         __syncthreads();
         float xd[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) xd[k] = 0.f;
         for (int q = 0; q < s; ++q) {
-            int jc = uni(w.ss[q]);
-            float dc = rdlane(dS, q);
+            const int jc = rdlane(jl, q);
+            const float dc = rdlane(dS, q);
 #pragma unroll
             for (int k = 0; k < R; ++k)
-                if (k < w.nslot) xd[k] = fmaf(w.Xs[jc * LDN + 64 * k + l], dc, xd[k]);
+                xd[k] = fmaf(w.Xs[jc * LDN + 64 * k + l], dc, xd[k]);
         }
         if (!type1) {
 #pragma unroll
-            for (int k = 0; k < R; ++k)
-                if (k < w.nslot) xd[k] = fmaf(w.Xs[sel * LDN + 64 * k + l], dj0, xd[k]);
+            for (int k = 0; k < R; ++k) xd[k] = fmaf(w.Xs[sel * LDN + 64 * k + l], dj0, xd[k]);
         }
-        const int zsel = type1 ? uni(w.zs[sel]) : -1;
+        const int zsel = type1 ? rdlane(zl, sel) : -1;
 #pragma unroll
         for (int k = 0; k < R; ++k)
             if ((zbits >> k) & 1u) xd[k] = (64 * k + l == zsel) ? -sgnf(usel) : 0.f;
@@ -898,9 +918,10 @@ LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, f
             }
         }
         __syncthreads();
+        const int zn = (l < s) ? w.zs[l] : 0;
         zbits = 0;
         for (int q = 0; q < s; ++q) {
-            int zq = uni(w.zs[q]);
+            const int zq = rdlane(zn, q);
             if ((zq & 63) == l) zbits |= 1u << (zq >> 6);
         }
         w.c_pivots++;
@@ -1024,8 +1045,7 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
                     ++round;
                     bbv = bv;
 #pragma unroll
-                    for (int kk = 0; kk < R; ++kk)
-                        if (kk < w.nslot) w.rbuf[64 * kk + l] = r[kk];
+                    for (int kk = 0; kk < R; ++kk) w.rbuf[64 * kk + l] = r[kk];
                     fbest = f;
                     chop_init(q, rdlane(bbv, kax), f, B);
                     more = chop_next(q, 0.f, sprobe, w.opt);
@@ -1035,22 +1055,20 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
                         fbest = f;
                         bbv = bv;
 #pragma unroll
-                        for (int kk = 0; kk < R; ++kk)
-                            if (kk < w.nslot) w.rbuf[64 * kk + l] = r[kk];
+                        for (int kk = 0; kk < R; ++kk) w.rbuf[64 * kk + l] = r[kk];
                     }
                     more = chop_next(q, f, sprobe, w.opt);
                 }
                 // next CCD starts from the best point; a probe sets b_kax := s
                 bv = bbv;
 #pragma unroll
-                for (int kk = 0; kk < R; ++kk) r[kk] = (kk < w.nslot) ? w.rbuf[64 * kk + l] : 0.f;
+                for (int kk = 0; kk < R; ++kk) r[kk] = w.rbuf[64 * kk + l];
                 if (more) {
                     const float d = sprobe - rdlane(bbv, kax);
                     if (d != 0.f) {
                         constexpr int LDN = Wave<R, XG>::LDN;
 #pragma unroll
-                        for (int kk = 0; kk < R; ++kk)
-                            if (kk < w.nslot) r[kk] = fmaf(-w.Xs[kax * LDN + 64 * kk + l], d, r[kk]);
+                        for (int kk = 0; kk < R; ++kk) r[kk] = fmaf(-w.Xs[kax * LDN + 64 * kk + l], d, r[kk]);
                     }
                     bv = (l == kax) ? sprobe : bv;
                     f = objective<R, XG>(w, r, bv);
@@ -1125,28 +1143,35 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
                 a.iters_out[4 * o + 3] = w.c_pivots;
             }
         }
-        if (l < 32) {
-            int val = -1;
-            if (zcount > 0 && l < zcount) {
-                int zl = w.zs[l], rank = 0;
-                for (int q = 0; q < zcount; ++q) rank += (uni(w.zs[q]) < zl) ? 1 : 0;
+        {
+            // Z rows in ascending order, -1 padded
+            const bool zr = zcount > 0 && l < zcount;
+            const int zl = zr ? w.zs[l] : INT_MAX;
+            int rank = 0;
+            for (int q = 0; q < zcount; ++q) rank += (rdlane(zl, q) < zl) ? 1 : 0;
+            if (zr)
                 a.zrows_out[(int64_t)ZPAD * o + rank] = zl;
-            } else {
-                a.zrows_out[(int64_t)ZPAD * o + l] = val;
-            }
+            else if (l < ZPAD)
+                a.zrows_out[(int64_t)ZPAD * o + l] = -1;
         }
         __syncthreads();
     }
 }
 
-// occupancy target (waves per SIMD) the register allocation must allow;
-// 0 leaves the choice to the compiler
+// occupancy target (waves per SIMD) the register allocation must allow:
+// a SIMD holds 512 registers per lane, so W waves need <= 512/W each
 #ifndef LADL_WAVES_PER_EU
 #define LADL_WAVES_PER_EU 0
 #endif
+__host__ __device__ constexpr int waves_per_eu(int R)
+{
+    // measured: R = 8 runs faster at 2 waves (no spills) than at 3 with
+    // spills; R = 16 gains from 2 waves despite a few spills
+    return LADL_WAVES_PER_EU > 0 ? LADL_WAVES_PER_EU : (R <= 2 ? 4 : R == 4 ? 3 : R == 16 ? 2 : 1);
+}
 
 template <int R, bool XG>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LADL_WAVES_PER_EU > 0 ? LADL_WAVES_PER_EU : 1)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
 void k_wave(SolveArgs a)
 {
     extern __shared__ float smem[];
@@ -1256,6 +1281,21 @@ int wave_max_blocks_per_cu(int R, int pmax, bool xg)
 // and every other entry of dL/dy and dL/dX is zero.  One wave per solve;
 // the dense zero fill dominates and streams at HBM write bandwidth.
 // --------------------------------------------------------------------------
+// Zero cnt floats at q with 16-byte streaming stores (scalar stores for the
+// unaligned head and the tail).
+__device__ __forceinline__ void zero_fill(float *q, int64_t cnt, int l)
+{
+    const int64_t head = min<int64_t>(cnt, (int64_t)((-(uintptr_t)q >> 2) & 3));
+    if (l < head) q[l] = 0.f;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    f4 *v = (f4 *)(q + head);
+    const int64_t m = (cnt - head) >> 2;
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t e = l; e < m; e += 64) __builtin_nontemporal_store(z, v + e);
+    const int64_t t = head + 4 * m + l;
+    if (t < cnt) q[t] = 0.f;
+}
+
 __global__ __launch_bounds__(64) void k_backward(BackwardArgs a)
 {
     __shared__ float A[32 * ALD];
@@ -1282,9 +1322,8 @@ __global__ __launch_bounds__(64) void k_backward(BackwardArgs a)
     if (ok && l < ns && (zl < 0 || zl >= n)) ok = false;
     ok = ballot(!ok) == 0;
     // dense zeros
-    const int np = n * p;
-    for (int e = l; e < np; e += 64) gX[e] = 0.f;
-    for (int i = l; i < n; i += 64) gy[i] = 0.f;
+    zero_fill(gX, n * p, l);
+    zero_fill(gy, n, l);
     if (!ok) return;
     // S in ascending order, one column index per lane c < ns
     int sc = -1;

@@ -184,11 +184,68 @@ __device__ __forceinline__ float wmin_nn(float v)
     return bitsf((int)~(uint32_t)__builtin_amdgcn_readlane((int)u, 63));
 }
 
-// double-precision sum (used only by the optimality certificate)
+// DPP move of a double (both halves; `old` is +0.0)
+template <int CTRL, int ROWM = 0xF>
+__device__ __forceinline__ double dppd(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWM, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWM, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double rdlane_d(double v, int l)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// double-precision sums (the optimality certificate and the final
+// objective), same fixed order as wsum; the four-way form interleaves
+// independent sums for latency
 __device__ __forceinline__ double wsum_d(double v)
 {
-    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
-    return v;
+    v += dppd<DPP_SHR1>(v);
+    v += dppd<DPP_SHR2>(v);
+    v += dppd<DPP_SHR4>(v);
+    v += dppd<DPP_SHR8>(v);
+    v += dppd<DPP_BCAST15, 0xA>(v);
+    v += dppd<DPP_BCAST31, 0xC>(v);
+    return rdlane_d(v, 63);
+}
+
+__device__ __forceinline__ void wsum_d4(double &a, double &b, double &c, double &d)
+{
+    a += dppd<DPP_SHR1>(a);
+    b += dppd<DPP_SHR1>(b);
+    c += dppd<DPP_SHR1>(c);
+    d += dppd<DPP_SHR1>(d);
+    a += dppd<DPP_SHR2>(a);
+    b += dppd<DPP_SHR2>(b);
+    c += dppd<DPP_SHR2>(c);
+    d += dppd<DPP_SHR2>(d);
+    a += dppd<DPP_SHR4>(a);
+    b += dppd<DPP_SHR4>(b);
+    c += dppd<DPP_SHR4>(c);
+    d += dppd<DPP_SHR4>(d);
+    a += dppd<DPP_SHR8>(a);
+    b += dppd<DPP_SHR8>(b);
+    c += dppd<DPP_SHR8>(c);
+    d += dppd<DPP_SHR8>(d);
+    a += dppd<DPP_BCAST15, 0xA>(a);
+    b += dppd<DPP_BCAST15, 0xA>(b);
+    c += dppd<DPP_BCAST15, 0xA>(c);
+    d += dppd<DPP_BCAST15, 0xA>(d);
+    a += dppd<DPP_BCAST31, 0xC>(a);
+    b += dppd<DPP_BCAST31, 0xC>(b);
+    c += dppd<DPP_BCAST31, 0xC>(c);
+    d += dppd<DPP_BCAST31, 0xC>(d);
+    a = rdlane_d(a, 63);
+    b = rdlane_d(b, 63);
+    c = rdlane_d(c, 63);
+    d = rdlane_d(d, 63);
 }
 
 // inclusive prefix sum across the 64 lanes (row shifts, then row
