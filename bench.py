@@ -33,13 +33,39 @@ METRIC = "LAD-LASSO solves/sec at 1e-5 rel objective vs plain kernel; achieved H
 def make_workload(cfg: str):
     from paper_2510_15649_amd import workloads as W
     return {"c1": lambda: W.config1(), "c1path": lambda: W.config1(as_path=True), "c2": lambda: W.config2(),
-            "c3": lambda: W.config3()}[cfg]()
+            "c3": lambda: W.config3(), "c4": lambda: W.config4(),
+            "c4s": lambda: W.config4(problems=range(C4_SAMPLE))}[cfg]()
+
+
+# problems of the 65536-problem ragged path workload timed by default (the
+# generator draws each problem independently, so the first 4096 are a
+# uniform sample of the full draw)
+C4_SAMPLE = 4096
+
+
+def log(msg):
+    """Progress to stderr (the JSON line is the only stdout output)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def backward_bytes(w, out_np, step):
+    """Algorithmic bytes of one backward launch: dL/dy and dL/dX written in
+    full (n + n p floats per problem); read per certified solve: g, b, the
+    zero-row list, status and the |S| x |S| vertex matrix."""
+    wr = 4 * (w.X.size + w.y.size)
+    L = w.path_len
+    act = out_np["active"].reshape(-1, L)[:, step]
+    ns = np.array([bin(int(a)).count("1") for a in act], dtype=np.int64)
+    ps = w.p[w.problem].astype(np.int64)
+    rd = int(np.sum(4 * (2 * ps + 32 + 1 + ns * ns)))
+    return int(wr + rd)
 
 
 def measure(L, torch, w, steps, warmup, parity_sample, autotune=False, **opts):
     """Times `steps` solves of workload w (after `warmup`), checks a seeded
     parity sample against the oracle.  Returns a dict."""
     from parity import compare, oracle_ref
+    log(f"{w.name}: {w.num_solves * w.path_len} solves, options {opts}")
     dev = torch.device("cuda:0")
     plan = L.Plan.for_workload(w, **opts)
     d = L.to_device(w, dev)
@@ -57,6 +83,7 @@ def measure(L, torch, w, steps, warmup, parity_sample, autotune=False, **opts):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
+    log(f"{w.name}: {ms:.3f} ms per step; checking {min(parity_sample, w.num_solves)} solves against the oracle")
     n_out = w.num_solves * w.path_len
     g = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
     it = g["iters"].reshape(-1, 4)
@@ -73,6 +100,44 @@ def measure(L, torch, w, steps, warmup, parity_sample, autotune=False, **opts):
                 describe=plan.describe())
 
 
+def path_graph_and_backward(L, torch, w, s, reps=5):
+    """For a path workload already measured by `measure`: the same path as a
+    replayed HIP graph (one launch per lambda step), and the backward kernel
+    at the last lambda timed against the HBM roofline."""
+    plan, d = s["plan"], s["d"]
+    stream = torch.cuda.current_stream()
+    out = plan.alloc_outputs(d["X"].device, iters=False)
+    graph = plan.graph(d["X"], d["y"], d["lam"], out)
+    graph.launch(stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    graph.launch(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1)
+    log(f"{w.name}: path as a HIP graph {graph_ms:.3f} ms")
+    step = w.path_len - 1
+    g = d["grad_b"]
+    gy = torch.empty(d["y"].numel(), dtype=torch.float32, device=d["X"].device)
+    gX = torch.empty_like(d["X"])
+    plan.backward(d["X"], out, g, step=step, grad_y=gy, grad_X=gX, stream=stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        plan.backward(d["X"], out, g, step=step, grad_y=gy, grad_X=gX, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    bms = e0.elapsed_time(e1) / reps
+    log(f"{w.name}: backward {bms:.3f} ms per launch")
+    onp = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    nbytes = backward_bytes(w, onp, step)
+    gbs = nbytes / (bms / 1e3) / 1e9
+    return graph_ms, {"workload": w.name, "kernel": "k_backward", "ms_per_launch": bms, "bound": "hbm",
+                      "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                      "traffic": None, "algorithmic_bytes": nbytes}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +151,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--parity-sample", type=int, default=256)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device (a known-size reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solves are independent, so a "
@@ -96,11 +163,24 @@ def main():
     import paper_2510_15649_amd as L
 
     assert torch.cuda.is_available()
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+        return
+    log(f"generating workload {args.config}")
     w = make_workload(args.config)
     flags = L.FLAG_GOLDEN if args.golden else 0
     m = measure(L, torch, w, args.steps, args.warmup, args.parity_sample, args.autotune,
                 max_rounds=args.max_rounds, flags=flags)
     ms = m["ms"]
+    main_graph_ms, main_backward = None, None
+    if w.path_len > 1 and w.grad_b is not None:
+        main_graph_ms, main_backward = path_graph_and_backward(L, torch, w, m)
     lane_ops = OPS_PER_ROW_UPDATE * m["row_updates"]
     achieved_ops = lane_ops / (ms / 1e3)
     alg_bytes = w.algorithmic_bytes()
@@ -108,6 +188,7 @@ def main():
 
     plain = None
     if not args.no_plain:
+        log("plain one-thread-per-solve kernel")
         from parity import compare, oracle_ref
         plan, d = m["plan"], m["d"]
         stream = torch.cuda.current_stream()
@@ -128,6 +209,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
+        log("oracle on the host cores")
         import oracle as O
         threads = min(os.cpu_count() or 1, 16)
         rng = np.random.default_rng(99)
@@ -144,16 +226,22 @@ def main():
                          f"(max_rounds={args.max_rounds}); {r['seconds']:.1f} s on {threads} threads"}
 
     secondary = []
+    backward = main_backward
     if not args.no_secondary:
-        for cfg, mr in [("c1", 0), ("c2", 1), ("c2", 0)]:
-            if cfg == args.config and mr == args.max_rounds:
+        for cfg, mr, fl in [("c1", 0, 0), ("c1", 1, L.FLAG_GOLDEN), ("c2", 1, 0), ("c2", 0, 0), ("c4s", 1, 0)]:
+            if cfg == args.config and mr == args.max_rounds and fl == flags:
                 continue
+            log(f"generating workload {cfg}")
             ws = make_workload(cfg)
-            s = measure(L, torch, ws, 3, 1, 128, args.autotune, max_rounds=mr)
-            secondary.append({"workload": ws.name, "max_rounds": mr, "solves_per_s": s["solves_per_s"],
-                              "ms_per_step": s["ms"], "parity_ok": s["parity_ok"],
-                              "max_rel_f": s["parity"]["max_rel_f"], "iters_mean": s["iters_mean"],
-                              "status": s["status"]})
+            big = cfg == "c4s"
+            s = measure(L, torch, ws, 2 if big else 3, 1, 8 if big else 128, args.autotune, max_rounds=mr, flags=fl)
+            entry = {"workload": ws.name, "max_rounds": mr, "golden": bool(fl), "solves_per_s": s["solves_per_s"],
+                     "ms_per_step": s["ms"], "parity_ok": s["parity_ok"], "max_rel_f": s["parity"]["max_rel_f"],
+                     "iters_mean": s["iters_mean"], "status": s["status"]}
+            if big:
+                entry["graph_ms_per_step"], bw = path_graph_and_backward(L, torch, ws, s)
+                backward = backward or bw
+            secondary.append(entry)
 
     line = {
         "metric": METRIC,
@@ -165,7 +253,8 @@ def main():
         "dtype": "f32", "data": "synthetic (seeded generator, no dataset)",
         "config": {"workload": w.name, "solves_per_step": m["n_out"], "max_rounds": args.max_rounds,
                    "golden": bool(args.golden), "autotune": bool(args.autotune),
-                   "parallelism": "1 GPU, one wavefront per solve"},
+                   "parallelism": "1 GPU, one wavefront per solve", "path_len": w.path_len,
+                   "graph_ms_per_step": main_graph_ms},
         "roofline": {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
                      "unit": "Tlane-op/s", "frac": achieved_ops / PEAK_VALU_LANE_OPS, "traffic": None,
                      "work_per_launch_lane_ops": lane_ops, "row_updates": m["row_updates"]},
@@ -179,6 +268,7 @@ def main():
         "status": m["status"],
         "iters_mean": m["iters_mean"],
         "secondary": secondary,
+        "roofline_backward": backward,
     }
     print(json.dumps(line), flush=True)
 

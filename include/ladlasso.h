@@ -174,8 +174,10 @@ int ladl_solve_plain_f32(ladl_plan_t plan, const float *X, const float *y, const
  * status is not LADL_CERTIFIED get zero gradients.
  *   b, zero_rows, status   device, the forward outputs (all steps)
  *   grad_b     device, packed like one path step of b
- *   grad_y     device, packed like y (output; fully written)
- *   grad_X     device, packed like X (output; fully written)
+ *   grad_y     device, packed like y (output; all y_len floats written,
+ *              zeros outside the vertex rows and outside every problem)
+ *   grad_X     device, packed like X (output; all x_len floats written,
+ *              likewise)
  * Every problem must be used by exactly one solve.
  */
 int ladl_backward_f32(ladl_plan_t plan, const float *X, const float *b, const int32_t *zero_rows,

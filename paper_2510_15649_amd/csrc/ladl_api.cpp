@@ -316,7 +316,10 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
     // plain kernel: all solves, decreasing cost
     std::vector<int32_t> order_plain(S);
     std::iota(order_plain.begin(), order_plain.end(), 0);
-    std::stable_sort(order_plain.begin(), order_plain.end(), cost_gt);
+    std::stable_sort(order_plain.begin(), order_plain.end(), [&](int a, int c) {
+        int ka = pl->problem[a], kc = pl->problem[c];
+        return (pl->row_off[ka + 1] - pl->row_off[ka]) * pl->p[ka] > (pl->row_off[kc + 1] - pl->row_off[kc]) * pl->p[kc];
+    });
     hipError_t e;
     std::vector<int32_t> zeros(pl->buckets.size() + 1, 0);
     if ((e = upload(&pl->d_row_off, pl->row_off)) != hipSuccess || (e = upload(&pl->d_x_off, pl->x_off)) != hipSuccess ||
@@ -541,6 +544,8 @@ int ladl_backward_f32(ladl_plan_t pl, const float *X, const float *b, const int3
     a.step = step;
     a.grad_y = grad_y;
     a.grad_X = grad_X;
+    a.x_len = pl->x_len;
+    a.y_len = pl->y_len;
     hipError_t e = launch_backward(a, (hipStream_t)stream);
     if (e != hipSuccess) return hipfail(e, "backward kernel launch");
     return LADL_OK;

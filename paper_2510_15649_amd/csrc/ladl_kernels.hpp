@@ -40,6 +40,7 @@ struct BackwardArgs {
     const int32_t *p_arr, *problem;
     int32_t num_solves, path_len, step;
     float *grad_y, *grad_X;
+    int64_t x_len, y_len; // floats of grad_X / grad_y, all written (zeros first)
 };
 
 // host-side launchers (defined in ladl_kernels.hip)

@@ -1281,19 +1281,21 @@ int wave_max_blocks_per_cu(int R, int pmax, bool xg)
 // and every other entry of dL/dy and dL/dX is zero.  One wave per solve;
 // the dense zero fill dominates and streams at HBM write bandwidth.
 // --------------------------------------------------------------------------
-// Zero cnt floats at q with 16-byte streaming stores (scalar stores for the
-// unaligned head and the tail).
-__device__ __forceinline__ void zero_fill(float *q, int64_t cnt, int l)
+// Dense zeros over [q, q + cnt): 16-byte streaming stores, grid-stride,
+// scalar stores for the unaligned head and the tail.
+__global__ __launch_bounds__(256) void k_zero_fill(float *q, int64_t cnt)
 {
-    const int64_t head = min<int64_t>(cnt, (int64_t)((-(uintptr_t)q >> 2) & 3));
-    if (l < head) q[l] = 0.f;
     typedef float f4 __attribute__((ext_vector_type(4)));
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    const int64_t head = min<int64_t>(cnt, (int64_t)((-(uintptr_t)q >> 2) & 3));
+    if (t < head) q[t] = 0.f;
     f4 *v = (f4 *)(q + head);
     const int64_t m = (cnt - head) >> 2;
     const f4 z = {0.f, 0.f, 0.f, 0.f};
-    for (int64_t e = l; e < m; e += 64) __builtin_nontemporal_store(z, v + e);
-    const int64_t t = head + 4 * m + l;
-    if (t < cnt) q[t] = 0.f;
+    for (int64_t e = t; e < m; e += nt) __builtin_nontemporal_store(z, v + e);
+    const int64_t tail = head + 4 * m + t;
+    if (tail < cnt) q[tail] = 0.f;
 }
 
 __global__ __launch_bounds__(64) void k_backward(BackwardArgs a)
@@ -1321,10 +1323,7 @@ __global__ __launch_bounds__(64) void k_backward(BackwardArgs a)
     bool ok = (status == ST_CERTIFIED) && ns == nz && ns > 0;
     if (ok && l < ns && (zl < 0 || zl >= n)) ok = false;
     ok = ballot(!ok) == 0;
-    // dense zeros
-    zero_fill(gX, n * p, l);
-    zero_fill(gy, n, l);
-    if (!ok) return;
+    if (!ok) return; // the zeros were written by k_zero_fill
     // S in ascending order, one column index per lane c < ns
     int sc = -1;
     if (l < p && bl != 0.f) sc = l;
@@ -1341,8 +1340,6 @@ __global__ __launch_bounds__(64) void k_backward(BackwardArgs a)
     const float g = (l < ns) ? a.grad_b[a.b_off[s] + sidx[l]] : 0.f;
     const float w = lu_solve_t(A, piv, ns, g); // lane q: w_q
     const float bS = (l < ns) ? b[sidx[l]] : 0.f;
-    // the zero fill must land before the non-zeros overwrite it
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     if (l < ns) gy[zl] = w;
     for (int c = 0; c < ns; ++c) {
         const float bc = rdlane(bS, c);
@@ -1350,9 +1347,20 @@ __global__ __launch_bounds__(64) void k_backward(BackwardArgs a)
     }
 }
 
+static hipError_t launch_zero_fill(float *q, int64_t cnt, hipStream_t s)
+{
+    if (cnt <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((cnt / 4 + 255) / 256 + 1, 8192);
+    hipLaunchKernelGGL(k_zero_fill, dim3((unsigned)blocks), dim3(256), 0, s, q, cnt);
+    return hipGetLastError();
+}
+
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_backward, dim3(a.num_solves), dim3(64), 0, s, a);
+    hipError_t e = launch_zero_fill(a.grad_X, a.x_len, s);
+    if (e == hipSuccess) e = launch_zero_fill(a.grad_y, a.y_len, s);
+    if (e != hipSuccess) return e;
+    if (a.num_solves > 0) hipLaunchKernelGGL(k_backward, dim3(a.num_solves), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
