@@ -131,7 +131,12 @@ void ladl_default_options(ladl_options *opt);
  * Validate a layout and build a plan: per-solve metadata uploaded to the
  * device, solves bucketed by rows per lane and sorted by decreasing cost
  * (n_k * p_k, then increasing lambda when lambda_hint is given) for the
- * persistent work queue, and the schedule chosen.
+ * persistent work queue, and the schedule chosen.  The plan owns device
+ * memory: the metadata, the queue counters, a workspace for buckets whose X
+ * does not fit LDS, and (when every problem is used by exactly one solve)
+ * 128 bytes per solve for the backward.  Calls on one plan share these, so
+ * calls on the same plan must not run concurrently on different streams;
+ * calls in stream order are fine.
  * Synchronous.  The plan keeps its own copies; layout arrays may be freed.
  */
 int ladl_plan_create(ladl_handle_t handle, const ladl_layout *layout, const ladl_options *opt,

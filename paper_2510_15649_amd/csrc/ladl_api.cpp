@@ -79,6 +79,7 @@ struct ladl_plan_s {
     int64_t gws_stride = 0;
     float *d_wws = nullptr;      // wave kernel workspace (buckets with X outside LDS)
     int64_t wws_floats = 0;
+    float *d_bw = nullptr;       // backward: 32 floats per solve (plans with each problem once)
     // buckets run concurrently on streams forked from the caller's stream
     std::vector<hipStream_t> bstreams;
     std::vector<hipEvent_t> ev_join;
@@ -185,6 +186,7 @@ static void plan_free_device(ladl_plan_s *pl)
     (void)hipFree(pl->d_counter_plain);
     (void)hipFree(pl->d_gws);
     (void)hipFree(pl->d_wws);
+    (void)hipFree(pl->d_bw);
     for (hipStream_t st : pl->bstreams) (void)hipStreamDestroy(st);
     for (hipEvent_t ev : pl->ev_join) (void)hipEventDestroy(ev);
     if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
@@ -336,6 +338,13 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         plan_free_device(pl);
         delete pl;
         return rc;
+    }
+    if (pl->problems_once && S > 0 &&
+        (e = hipMalloc((void **)&pl->d_bw, sizeof(float) * 32 * (size_t)S)) != hipSuccess) {
+        pl->d_bw = nullptr;
+        plan_free_device(pl);
+        delete pl;
+        return hipfail(e, "backward buffer");
     }
     if (pl->buckets.size() > 1) {
         pl->bstreams.resize(pl->buckets.size(), nullptr);
@@ -546,6 +555,7 @@ int ladl_backward_f32(ladl_plan_t pl, const float *X, const float *b, const int3
     a.grad_X = grad_X;
     a.x_len = pl->x_len;
     a.y_len = pl->y_len;
+    a.bw = pl->d_bw;
     hipError_t e = launch_backward(a, (hipStream_t)stream);
     if (e != hipSuccess) return hipfail(e, "backward kernel launch");
     return LADL_OK;

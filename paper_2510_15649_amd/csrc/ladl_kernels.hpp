@@ -41,6 +41,7 @@ struct BackwardArgs {
     int32_t num_solves, path_len, step;
     float *grad_y, *grad_X;
     int64_t x_len, y_len; // floats of grad_X / grad_y, all written (zeros first)
+    float *bw;            // 32 floats per solve: w of the vertex solve (NaN: none)
 };
 
 // host-side launchers (defined in ladl_kernels.hip)

@@ -1278,89 +1278,132 @@ int wave_max_blocks_per_cu(int R, int pmax, bool xg)
 // H10: gradient through the optimal vertex.  At a certified vertex b_S =
 // X_{Z,S}^{-1} y_Z (the vertex form of Section 3.2), so for a loss L with
 // g = dL/db:  w = X_{Z,S}^{-T} g_S,  dL/dy_Z = w,  dL/dX_{Z,S} = -w b_S^T,
-// and every other entry of dL/dy and dL/dX is zero.  One wave per solve;
-// the dense zero fill dominates and streams at HBM write bandwidth.
+// and every other entry of dL/dy and dL/dX is zero.
+// Two launches: k_bw_vertex runs the dense zero fill (blocks below
+// fill_blocks, grid-stride, HBM-bound) side by side with the per-solve
+// vertex solves (one wave each, latency-bound), which leave w in a small
+// per-solve buffer; k_bw_scatter then writes the few non-zeros.
 // --------------------------------------------------------------------------
-// Dense zeros over [q, q + cnt): 16-byte streaming stores, grid-stride,
-// scalar stores for the unaligned head and the tail.
-__global__ __launch_bounds__(256) void k_zero_fill(float *q, int64_t cnt)
+
+// The vertex of solve s as the backward sees it: lane c < ns holds the
+// c-th column of S (ascending) in sc and b at it in bS; lane q < ns holds
+// the q-th zero row in zl.  Returns false (uniformly) when the solve has
+// no certified vertex.
+struct BwVertex {
+    int n, p, ns, zl, sc;
+    float bS;
+    int64_t x_off, r0, b_base;
+};
+
+__device__ __forceinline__ bool bw_vertex(const BackwardArgs &a, int s, BwVertex &v)
 {
-    typedef float f4 __attribute__((ext_vector_type(4)));
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
-    const int64_t head = min<int64_t>(cnt, (int64_t)((-(uintptr_t)q >> 2) & 3));
-    if (t < head) q[t] = 0.f;
-    f4 *v = (f4 *)(q + head);
-    const int64_t m = (cnt - head) >> 2;
-    const f4 z = {0.f, 0.f, 0.f, 0.f};
-    for (int64_t e = t; e < m; e += nt) __builtin_nontemporal_store(z, v + e);
-    const int64_t tail = head + 4 * m + t;
-    if (tail < cnt) q[tail] = 0.f;
+    const int l = lane_id();
+    const int k = a.problem ? a.problem[s] : s;
+    v.r0 = a.row_off[k];
+    v.n = (int)(a.row_off[k + 1] - v.r0);
+    v.p = a.p_arr[k];
+    v.x_off = a.x_off[k];
+    const int64_t o = (int64_t)s * a.path_len + a.step;
+    v.b_base = (int64_t)a.path_len * a.b_off[s] + (int64_t)a.step * v.p;
+    const int status = a.status[o];
+    const float bl = (l < v.p) ? a.b[v.b_base + l] : 0.f;
+    const uint64_t sb = ballot(l < v.p && bl != 0.f);
+    v.ns = popc64(sb);
+    v.zl = (l < ZPAD) ? a.zrows[(int64_t)ZPAD * o + l] : -1;
+    const int nz = popc64(ballot(l < ZPAD && v.zl >= 0));
+    bool ok = (status == ST_CERTIFIED) && v.ns == nz && v.ns > 0;
+    if (ok && l < v.ns && (v.zl < 0 || v.zl >= v.n)) ok = false;
+    ok = ballot(!ok) == 0;
+    // the c-th set bit of the S mask, for lane c
+    uint64_t t = sb;
+    v.sc = 0;
+    for (int c = 0; c < v.ns; ++c) {
+        const int j = (int)__builtin_ctzll(t);
+        t &= t - 1;
+        v.sc = (l == c) ? j : v.sc;
+    }
+    v.bS = (l < v.ns) ? a.b[v.b_base + v.sc] : 0.f;
+    return ok;
 }
 
-__global__ __launch_bounds__(64) void k_backward(BackwardArgs a)
+__global__ __launch_bounds__(64) void k_bw_vertex(BackwardArgs a, int fill_blocks)
 {
+    const int l = lane_id();
+    if ((int)blockIdx.x < fill_blocks) {
+        // dense zeros: 16-byte streaming stores, scalar head and tail
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const int64_t t = (int64_t)blockIdx.x * 64 + l, nt = (int64_t)fill_blocks * 64;
+        const f4 z = {0.f, 0.f, 0.f, 0.f};
+        float *qs[2] = {a.grad_X, a.grad_y};
+        const int64_t cs[2] = {a.x_len, a.y_len};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            float *q = qs[u];
+            const int64_t cnt = cs[u];
+            const int64_t head = min<int64_t>(cnt, (int64_t)((-(uintptr_t)q >> 2) & 3));
+            if (t < head) q[t] = 0.f;
+            f4 *vq = (f4 *)(q + head);
+            const int64_t m = (cnt - head) >> 2;
+            for (int64_t e = t; e < m; e += nt) __builtin_nontemporal_store(z, vq + e);
+            const int64_t tail = head + 4 * m + t;
+            if (tail < cnt) q[tail] = 0.f;
+        }
+        return;
+    }
     __shared__ float A[32 * ALD];
     __shared__ int piv[32];
+    const int s = (int)blockIdx.x - fill_blocks;
+    if (s >= a.num_solves) return;
+    float *wout = a.bw + (int64_t)32 * s;
+    BwVertex v;
+    bool ok = bw_vertex(a, s, v);
+    if (ok) {
+        const float *X = a.X + v.x_off;
+        // A[q][c] = x_{Z_q, S_c}: lane c gathers its column
+        for (int q = 0; q < v.ns; ++q) {
+            const int zq = rdlane(v.zl, q);
+            if (l < v.ns) A[q * ALD + l] = X[(int64_t)zq * v.p + v.sc];
+        }
+        __syncthreads();
+        ok = lu_factor(A, piv, v.ns);
+    }
+    if (!ok) {
+        if (l == 0) wout[0] = __builtin_nanf(""); // no gradient for this solve
+        return;
+    }
+    const float g = (l < v.ns) ? a.grad_b[a.b_off[s] + v.sc] : 0.f;
+    const float w = lu_solve_t(A, piv, v.ns, g); // lane q: w_q
+    if (l < 32) wout[l] = (l < v.ns) ? w : 0.f;
+}
+
+__global__ __launch_bounds__(64) void k_bw_scatter(BackwardArgs a)
+{
     const int l = lane_id();
     const int s = blockIdx.x;
     if (s >= a.num_solves) return;
-    const int k = a.problem ? a.problem[s] : s;
-    const int64_t r0 = a.row_off[k];
-    const int n = (int)(a.row_off[k + 1] - r0);
-    const int p = a.p_arr[k];
-    const float *X = a.X + a.x_off[k];
-    float *gX = a.grad_X + a.x_off[k];
-    float *gy = a.grad_y + r0;
-    const int64_t o = (int64_t)s * a.path_len + a.step;
-    const float *b = a.b + (int64_t)a.path_len * a.b_off[s] + (int64_t)a.step * p;
-    const int status = a.status[o];
-    const float bl = (l < p) ? b[l] : 0.f;
-    const uint64_t sb = ballot(l < p && bl != 0.f);
-    int ns = popc64(sb);
-    const int zl = (l < ZPAD) ? a.zrows[(int64_t)ZPAD * o + l] : -1;
-    const int nz = popc64(ballot(l < ZPAD && zl >= 0));
-    bool ok = (status == ST_CERTIFIED) && ns == nz && ns > 0;
-    if (ok && l < ns && (zl < 0 || zl >= n)) ok = false;
-    ok = ballot(!ok) == 0;
-    if (!ok) return; // the zeros were written by k_zero_fill
-    // S in ascending order, one column index per lane c < ns
-    int sc = -1;
-    if (l < p && bl != 0.f) sc = l;
-    const int cpos = mbcnt(sb); // position of lane l's column among S
-    __shared__ int sidx[32];
-    if (sc >= 0) sidx[cpos] = sc;
-    __syncthreads();
-    for (int q = 0; q < ns; ++q) {
-        const int zq = rdlane(zl, q);
-        if (l < ns) A[q * ALD + l] = X[(int64_t)zq * p + sidx[l]];
+    BwVertex v;
+    if (!bw_vertex(a, s, v)) return;
+    const float w = (l < v.ns) ? a.bw[(int64_t)32 * s + l] : 0.f;
+    if (!__builtin_isfinite(rdlane(w, 0))) return;
+    if (ballot(l < v.ns && !__builtin_isfinite(w))) return;
+    float *gX = a.grad_X + v.x_off;
+    float *gy = a.grad_y + v.r0;
+    if (l < v.ns) gy[v.zl] = w;
+    for (int c = 0; c < v.ns; ++c) {
+        const float bc = rdlane(v.bS, c);
+        const int jc = rdlane(v.sc, c);
+        if (l < v.ns) gX[(int64_t)v.zl * v.p + jc] = -w * bc;
     }
-    __syncthreads();
-    if (!lu_factor(A, piv, ns)) return;
-    const float g = (l < ns) ? a.grad_b[a.b_off[s] + sidx[l]] : 0.f;
-    const float w = lu_solve_t(A, piv, ns, g); // lane q: w_q
-    const float bS = (l < ns) ? b[sidx[l]] : 0.f;
-    if (l < ns) gy[zl] = w;
-    for (int c = 0; c < ns; ++c) {
-        const float bc = rdlane(bS, c);
-        if (l < ns) gX[(int64_t)zl * p + sidx[c]] = -w * bc;
-    }
-}
-
-static hipError_t launch_zero_fill(float *q, int64_t cnt, hipStream_t s)
-{
-    if (cnt <= 0) return hipSuccess;
-    const int64_t blocks = std::min<int64_t>((cnt / 4 + 255) / 256 + 1, 8192);
-    hipLaunchKernelGGL(k_zero_fill, dim3((unsigned)blocks), dim3(256), 0, s, q, cnt);
-    return hipGetLastError();
 }
 
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s)
 {
-    hipError_t e = launch_zero_fill(a.grad_X, a.x_len, s);
-    if (e == hipSuccess) e = launch_zero_fill(a.grad_y, a.y_len, s);
+    const int64_t f4s = (a.x_len + a.y_len) / 4 + 2;
+    const int fill_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((f4s + 63) / 64, 2048));
+    hipLaunchKernelGGL(k_bw_vertex, dim3(fill_blocks + a.num_solves), dim3(64), 0, s, a, fill_blocks);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (a.num_solves > 0) hipLaunchKernelGGL(k_backward, dim3(a.num_solves), dim3(64), 0, s, a);
+    if (a.num_solves > 0) hipLaunchKernelGGL(k_bw_scatter, dim3(a.num_solves), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
