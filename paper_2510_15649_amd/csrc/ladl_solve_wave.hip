@@ -208,8 +208,8 @@ LADL_INL float objective(Wave<R, XG> &w, const float (&r)[R], float bval)
 
 // --------------------------------------------------------------------------
 // Weighted selection over the wave.
-// Candidates: per-lane register keys a[k] (FINF = none) with weights wt[k],
-// plus one extra key (av, wv) per lane.  All keys are >= 0.  Returns the
+// Candidates: per-lane register keys a[k] (FINF = none) with weights
+// |x[k]| (zero for FINF keys), plus one extra key (av, wv) per lane.  All keys are >= 0.  Returns the
 // smallest key a* whose cumulative weight (over keys <= a*) reaches T
 // (strict: exceeds T), and which register slot or extra key holds it
 // (row keys win ties against extra keys).
@@ -245,9 +245,11 @@ LADL_INL Sel owner_of(const float (&a)[R], float av, float m)
 }
 
 template <int R, bool XG>
-LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&wt)[R], float av, float wv, float T,
+LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&x)[R], float av, float wv, float T,
                        bool strict, float lo0, float cum0)
 {
+    // weights are recomputed where used rather than held in R more registers
+    auto wt = [&](int k) { return (a[k] < FINF) ? fabsf(x[k]) : 0.f; };
     const int l = lane_id();
     float lo = lo0, hi = FINF, cum = cum0;
     auto reached = [&](float c) { return strict ? (c > T) : (c >= T); };
@@ -264,7 +266,7 @@ LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&wt)[R], 
         }
         float wm = 0.f;
 #pragma unroll
-        for (int k = 0; k < R; ++k) wm += (a[k] == m) ? wt[k] : 0.f;
+        for (int k = 0; k < R; ++k) wm += (a[k] == m) ? wt(k) : 0.f;
         wm += (av == m) ? wv : 0.f;
         wm = wsum(wm);
         if (reached(cum + wm)) return owner_of<R, XG>(a, av, m);
@@ -284,7 +286,7 @@ LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&wt)[R], 
         for (int k = R - 1; k >= 0; --k) {
             bool in = a[k] > lo && a[k] <= hi;
             smp = in ? a[k] : smp;
-            wint += in ? wt[k] : 0.f;
+            wint += in ? wt(k) : 0.f;
         }
         if (av > lo && av <= hi) {
             smp = (smp == FINF) ? av : smp;
@@ -302,8 +304,8 @@ LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&wt)[R], 
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             bool in = a[k] > lo && a[k] <= hi;
-            c1 += (in && a[k] <= p1) ? wt[k] : 0.f;
-            c2 += (in && a[k] <= p2) ? wt[k] : 0.f;
+            c1 += (in && a[k] <= p1) ? wt(k) : 0.f;
+            c2 += (in && a[k] <= p2) ? wt(k) : 0.f;
         }
         if (av > lo && av <= hi) {
             c1 += (av <= p1) ? wv : 0.f;
@@ -334,7 +336,7 @@ LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&wt)[R], 
             if (m == FINF) break;
             float wm = 0.f;
 #pragma unroll
-            for (int k = 0; k < R; ++k) wm += (a[k] == m) ? wt[k] : 0.f;
+            for (int k = 0; k < R; ++k) wm += (a[k] == m) ? wt(k) : 0.f;
             wm += (av == m) ? wv : 0.f;
             wm = wsum(wm);
             if (reached(cum + wm) || m == hi) return owner_of<R, XG>(a, av, m);
@@ -352,7 +354,7 @@ LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&wt)[R], 
         if (in) {
             int pos = base + mbcnt(bal);
             w.sa[pos] = a[k];
-            w.sw[pos] = wt[k];
+            w.sw[pos] = wt(k);
         }
         base += popc64(bal);
     }
@@ -464,12 +466,9 @@ LADL_INL bool coord_update(Wave<R, XG> &w, float (&r)[R], float &bv, int j, cons
         }
         nb = virt ? 0.f : (down ? bj - mm : bj + mm);
     } else {
-        float wt[R];
-#pragma unroll
-        for (int k = 0; k < R; ++k) wt[k] = (a[k] < FINF) ? fabsf(x[k]) : 0.f;
         const float av = (l == 0 && lcand) ? al : FINF;
         const float wv = (l == 0 && lcand) ? lam : 0.f;
-        Sel sl = wselect<R, XG>(w, a, wt, av, wv, T, down, mm, wm);
+        Sel sl = wselect<R, XG>(w, a, x, av, wv, T, down, mm, wm);
         if (!(sl.a < FINF)) return false;
         virt = sl.virt;
         olane = sl.lane;
@@ -873,20 +872,18 @@ LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, f
         const float bl = (l < p) ? w.vt[l] : 0.f;
         const float need = -0.5f * m;
         if (!(need > 0.f)) return ST_NOTCERT;
-        float a[R], wt[R];
+        float a[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             bool pos = rv[k] != 0.f && xd[k] != 0.f &&
                        __builtin_signbit(rv[k]) == __builtin_signbit(xd[k]);
-            float ax = fabsf(xd[k]);
-            a[k] = pos ? fabsf(rv[k]) / ax : FINF;
-            wt[k] = pos ? ax : 0.f;
+            a[k] = pos ? fabsf(rv[k]) / fabsf(xd[k]) : FINF; // weight |xd_i|
         }
         const bool vpos = (l < p) && lam > 0.f && dl != 0.f && bl != 0.f &&
                           __builtin_signbit(bl) != __builtin_signbit(dl);
         const float av = vpos ? fabsf(bl) / fabsf(dl) : FINF;
         const float wv = vpos ? lam * fabsf(dl) : 0.f;
-        Sel sr = wselect<R, XG>(w, a, wt, av, wv, need, false, -1.f, 0.f);
+        Sel sr = wselect<R, XG>(w, a, xd, av, wv, need, false, -1.f, 0.f);
         if (!(sr.a > 0.f) || sr.a == FINF) return ST_NOTCERT;
         // new vertex
         if (type1) {
@@ -1158,17 +1155,15 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
     }
 }
 
-// occupancy target (waves per SIMD) the register allocation must allow:
-// a SIMD holds 512 registers per lane, so W waves need <= 512/W each
+// Optional occupancy target (waves per SIMD) imposed on the register
+// allocation; 0 (default) leaves it to the compiler.  Measured on the
+// ragged workloads: an explicit target, even one the allocation already
+// meets, made the n <= 1024 bucket slower (2.3x in the vertex phase), so
+// none is set.
 #ifndef LADL_WAVES_PER_EU
 #define LADL_WAVES_PER_EU 0
 #endif
-__host__ __device__ constexpr int waves_per_eu(int R)
-{
-    // measured: R = 8 runs faster at 2 waves (no spills) than at 3 with
-    // spills; R = 16 gains from 2 waves despite a few spills
-    return LADL_WAVES_PER_EU > 0 ? LADL_WAVES_PER_EU : (R <= 2 ? 4 : R == 4 ? 3 : R == 16 ? 2 : 1);
-}
+__host__ __device__ constexpr int waves_per_eu(int) { return LADL_WAVES_PER_EU > 0 ? LADL_WAVES_PER_EU : 1; }
 
 template <int R, bool XG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
