@@ -9,10 +9,11 @@ problems (n=200, p=8) x 16 lambdas = 8192 solves with the paper's schedule
 Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
-import time
 
 import numpy as np
 
@@ -41,6 +42,36 @@ def make_workload(cfg: str):
 # generator draws each problem independently, so the first 4096 are a
 # uniform sample of the full draw)
 C4_SAMPLE = 4096
+
+
+# device sources whose hash the committed byte-counter summaries record
+KERNEL_SOURCES = ["ladl_solve_wave.hip", "ladl_wave.hpp", "ladl_common.hpp", "ladl_kernels.hpp"]
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_15649_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(summary, key):
+    """HBM bytes per launch that a committed rocprofv3 summary under
+    profiles/ records for `key` (FETCH_SIZE + WRITE_SIZE, scaled by a copy
+    of known size), or None when the kernel sources changed since."""
+    vals = {}
+    try:
+        with open(os.path.join(ROOT, "profiles", summary)) as fh:
+            for line in fh:
+                m = re.match(r"^\s*-\s*(\w+):\s*(\S+)\s*$", line)
+                if m:
+                    vals[m.group(1)] = m.group(2)
+    except OSError:
+        return None
+    if vals.get("source_sha256") != kernel_source_sha() or key not in vals:
+        return None
+    return int(vals[key])
 
 
 def log(msg):
@@ -185,6 +216,8 @@ def main():
     achieved_ops = lane_ops / (ms / 1e3)
     alg_bytes = w.algorithmic_bytes()
     hbm_gbs = alg_bytes / (ms / 1e3) / 1e9
+    default_c1 = args.config == "c1" and args.max_rounds == 1 and not args.golden and not args.autotune
+    traffic = recorded_traffic("k_wave_c1_hbm_bytes.md", "traffic_bytes_per_launch") if default_c1 else None
 
     plain = None
     if not args.no_plain:
@@ -240,6 +273,7 @@ def main():
                      "iters_mean": s["iters_mean"], "status": s["status"]}
             if big:
                 entry["graph_ms_per_step"], bw = path_graph_and_backward(L, torch, ws, s)
+                bw["traffic"] = recorded_traffic("c4_sample_kernel_stats.md", "backward_traffic_bytes_per_launch")
                 backward = backward or bw
             secondary.append(entry)
 
@@ -256,7 +290,7 @@ def main():
                    "parallelism": "1 GPU, one wavefront per solve", "path_len": w.path_len,
                    "graph_ms_per_step": main_graph_ms},
         "roofline": {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
-                     "unit": "Tlane-op/s", "frac": achieved_ops / PEAK_VALU_LANE_OPS, "traffic": None,
+                     "unit": "Tlane-op/s", "frac": achieved_ops / PEAK_VALU_LANE_OPS, "traffic": traffic,
                      "work_per_launch_lane_ops": lane_ops, "row_updates": m["row_updates"]},
         "hbm": {"achieved_GBs": hbm_gbs, "peak_GBs": PEAK_HBM_GBS, "frac": hbm_gbs / PEAK_HBM_GBS,
                 "algorithmic_bytes": alg_bytes},
