@@ -169,6 +169,44 @@ def path_graph_and_backward(L, torch, w, s, reps=5):
                       "traffic": None, "algorithmic_bytes": nbytes}
 
 
+def measure_cv(L, torch, folds=5, steps=3, sample=4):
+    """K-fold cross-validation of the 512 c1 problems along their 16-lambda
+    path (the training solves run on the wave kernels); parity of the fold
+    errors on a few problems against the oracle's cross-validation."""
+    import oracle as O
+    from paper_2510_15649_amd import workloads as W
+    w = W.config1(as_path=True)
+    log(f"cross-validation: {w.num_problems} problems x {folds} folds x {w.path_len} lambdas")
+    cv = L.CrossValidation.for_workload(w, folds)
+    d = L.to_device(w)
+    stream = torch.cuda.current_stream()
+    out = cv.run(d["X"], d["y"], d["lam"], stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        out = cv.run(d["X"], d["y"], d["lam"], stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    Lp, P = w.path_len, w.num_problems
+    ferr = g["fold_error"].reshape(P, folds, Lp)
+    worst = 0.0
+    for k in range(sample):
+        Xk, yk = w.block(k)
+        ref = O.cv(Xk, yk, w.lam[k * Lp:(k + 1) * Lp], folds, max_rounds=0)
+        u = ref["unique"]
+        rel = np.abs(ferr[k][u] - ref["err"][u]) / np.maximum(1.0, ref["err"][u])
+        worst = max(worst, float(rel.max()) if rel.size else 0.0)
+    st = g["fold_status"]
+    return {"workload": f"cross-validation of {w.name} (as a path), {folds} folds", "ms_per_step": ms,
+            "selections_per_s": P / (ms / 1e3), "training_solves_per_s": P * folds * Lp / (ms / 1e3),
+            "parity_sample_problems": sample, "max_rel_fold_error": worst, "parity_ok": worst <= 1e-5,
+            "certified_or_nonunique": int(np.sum((st == L.CERTIFIED) | (st == L.NONUNIQUE))),
+            "training_solves": int(st.size)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,6 +314,7 @@ def main():
                 bw["traffic"] = recorded_traffic("c4_sample_kernel_stats.md", "backward_traffic_bytes_per_launch")
                 backward = backward or bw
             secondary.append(entry)
+        secondary.append(measure_cv(L, torch))
 
     line = {
         "metric": METRIC,

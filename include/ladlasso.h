@@ -215,6 +215,59 @@ int ladl_plan_describe(ladl_plan_t plan, char *buf, int64_t buf_len);
 const char *ladl_error_string(int code);
 const char *ladl_last_error_detail(void);
 
+/*
+ * K-fold cross-validation along a lambda path, all on the device: the
+ * paper's interactive use of several regularisation settings solved while
+ * cross-validating (Section 5).  For every base problem k and fold f, the
+ * rows outside f form a training problem solved along the path (each step
+ * warm-started from the previous one, same method and status codes as
+ * ladl_solve_f32); the rows in f score every step's b by the held-out
+ * absolute error  e[k,f,t] = sum_{i in f} |y_i - x_i . b_{k,f}(lambda_t)|
+ * (fp32 residuals, fp64 sums).  The CV curve is cv[k,t] = sum_f e[k,f,t]
+ * and best[k] is its first minimiser.
+ *
+ * The base layout is that of ladl_layout (one solve per problem).  Fold of
+ * local row i of problem k: fold_of_row[row_off[k] + i] when given, else
+ * i mod folds.  Every fold must leave at least one training row, and a
+ * training problem obeys the solver's limits (n <= 2048, p <= 32).
+ * The object owns device memory: the training problems' X and y (K - 1
+ * times the base data), their solver plan and its outputs.  Calls on one
+ * object run in stream order, not concurrently.  Solver options apply to
+ * every training solve.
+ */
+typedef struct ladl_cv_s *ladl_cv_t;
+
+typedef struct {
+    int32_t num_problems;
+    const int64_t *row_off;     /* host [num_problems+1], as in ladl_layout              */
+    const int64_t *x_off;       /* host [num_problems] or NULL                           */
+    const int32_t *p;           /* host [num_problems] or NULL: p_uniform                */
+    int32_t p_uniform;
+    int64_t x_len;              /* floats in X (bounds check)                            */
+    int64_t y_len;              /* floats in y (bounds check)                            */
+    int32_t folds;              /* K, 2 .. 64                                            */
+    const int32_t *fold_of_row; /* host [row_off[num_problems]] or NULL: i mod K          */
+    int32_t path_len;           /* L, 1 .. 64                                            */
+} ladl_cv_layout;
+
+int ladl_cv_create(ladl_handle_t handle, const ladl_cv_layout *layout, const ladl_options *opt,
+                   ladl_cv_t *cv);
+int ladl_cv_destroy(ladl_cv_t cv);
+
+/*
+ *   X, y        device, the base problems (as for ladl_solve_f32)
+ *   lambda      device [num_problems * path_len], the path of each problem
+ *   fold_error  device [num_problems * K * path_len] or NULL: e[k,f,t] at
+ *               (k*K + f)*path_len + t (output)
+ *   cv_error    device [num_problems * path_len]: cv[k,t] (output)
+ *   best        device [num_problems]: first t minimising cv[k,t] (output)
+ *   fold_status device [num_problems * K * path_len] or NULL: the solver
+ *               status of each training solve, same indexing (output)
+ * Enqueued on `stream`; nothing is synchronised.
+ */
+int ladl_cv_run(ladl_cv_t cv, const float *X, const float *y, const float *lambda, float *fold_error,
+                float *cv_error, int32_t *best, int32_t *fold_status, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

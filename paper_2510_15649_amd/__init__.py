@@ -28,7 +28,8 @@ ZPAD = 32
 EXPORTED = ["ladl_create", "ladl_destroy", "ladl_default_options", "ladl_plan_create", "ladl_plan_destroy",
             "ladl_plan_b_len", "ladl_solve_f32", "ladl_solve_plain_f32", "ladl_backward_f32",
             "ladl_graph_create", "ladl_graph_launch", "ladl_graph_destroy", "ladl_autotune",
-            "ladl_plan_describe", "ladl_error_string", "ladl_last_error_detail"]
+            "ladl_plan_describe", "ladl_error_string", "ladl_last_error_detail", "ladl_cv_create",
+            "ladl_cv_destroy", "ladl_cv_run"]
 
 
 class Options(C.Structure):
@@ -46,6 +47,13 @@ class Layout(C.Structure):
                 ("x_len", C.c_int64), ("y_len", C.c_int64), ("num_solves", C.c_int32),
                 ("problem", C.POINTER(C.c_int32)), ("path_len", C.c_int32),
                 ("lambda_hint", C.POINTER(C.c_float))]
+
+
+class CVLayout(C.Structure):
+    _fields_ = [("num_problems", C.c_int32), ("row_off", C.POINTER(C.c_int64)),
+                ("x_off", C.POINTER(C.c_int64)), ("p", C.POINTER(C.c_int32)), ("p_uniform", C.c_int32),
+                ("x_len", C.c_int64), ("y_len", C.c_int64), ("folds", C.c_int32),
+                ("fold_of_row", C.POINTER(C.c_int32)), ("path_len", C.c_int32)]
 
 
 class LadlError(RuntimeError):
@@ -84,13 +92,17 @@ def lib() -> C.CDLL:
     L.ladl_graph_destroy.argtypes = [vp]
     L.ladl_autotune.argtypes = [vp] + [vp] * 9
     L.ladl_plan_describe.argtypes = [vp, C.c_char_p, i64]
+    L.ladl_cv_create.argtypes = [vp, C.POINTER(CVLayout), C.POINTER(Options), C.POINTER(vp)]
+    L.ladl_cv_destroy.argtypes = [vp]
+    L.ladl_cv_run.argtypes = [vp] + [vp] * 7 + [vp]
     L.ladl_error_string.argtypes = [C.c_int]
     L.ladl_error_string.restype = C.c_char_p
     L.ladl_last_error_detail.argtypes = []
     L.ladl_last_error_detail.restype = C.c_char_p
     for name in ["ladl_create", "ladl_destroy", "ladl_plan_create", "ladl_plan_destroy", "ladl_solve_f32",
                  "ladl_solve_plain_f32", "ladl_backward_f32", "ladl_graph_create", "ladl_graph_launch",
-                 "ladl_graph_destroy", "ladl_autotune", "ladl_plan_describe"]:
+                 "ladl_graph_destroy", "ladl_autotune", "ladl_plan_describe", "ladl_cv_create", "ladl_cv_destroy",
+                 "ladl_cv_run"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -295,6 +307,67 @@ class PathGraph:
         if getattr(self, "_g", None) and _lib is not None:
             _lib.ladl_graph_destroy(self._g)
             self._g = None
+
+
+class CrossValidation:
+    """K-fold cross-validation of every problem along its lambda path, on the
+    device (gather of the training problems, wave-kernel solves, held-out
+    scoring, selection).  Host layout arrays are copied at creation.
+
+    row_off, p, x_off, x_len, y_len   the base problems, as for Plan
+    folds         K
+    path_len      lambdas per problem
+    fold_of_row   int32 [total rows] or None (local row i -> fold i mod K)
+    """
+
+    def __init__(self, row_off, p, *, x_len: int, y_len: int, folds: int, path_len: int, x_off=None,
+                 fold_of_row=None, options: Optional[Options] = None, handle: Optional[Handle] = None, **opt_kw):
+        self.handle = handle or default_handle()
+        self.options = options if options is not None else default_options(**opt_kw)
+        self._row_off = np.ascontiguousarray(row_off, dtype=np.int64)
+        P = self._row_off.shape[0] - 1
+        self._p = None if np.isscalar(p) else np.ascontiguousarray(p, dtype=np.int32)
+        self._x_off = None if x_off is None else np.ascontiguousarray(x_off, dtype=np.int64)
+        self._fold = None if fold_of_row is None else np.ascontiguousarray(fold_of_row, dtype=np.int32)
+        lay = CVLayout()
+        lay.num_problems = P
+        lay.row_off = self._row_off.ctypes.data_as(C.POINTER(C.c_int64))
+        lay.x_off = None if self._x_off is None else self._x_off.ctypes.data_as(C.POINTER(C.c_int64))
+        lay.p = None if self._p is None else self._p.ctypes.data_as(C.POINTER(C.c_int32))
+        lay.p_uniform = int(p) if np.isscalar(p) else int(self._p[0])
+        lay.x_len, lay.y_len = int(x_len), int(y_len)
+        lay.folds = int(folds)
+        lay.fold_of_row = None if self._fold is None else self._fold.ctypes.data_as(C.POINTER(C.c_int32))
+        lay.path_len = int(path_len)
+        h = C.c_void_p()
+        check(lib().ladl_cv_create(self.handle.ptr, C.byref(lay), C.byref(self.options), C.byref(h)))
+        self._cv = h
+        self.num_problems, self.folds, self.path_len = P, int(folds), int(path_len)
+
+    @classmethod
+    def for_workload(cls, w, folds: int, **kw) -> "CrossValidation":
+        """Base problems of a Workload whose solves walk each problem's path."""
+        return cls(w.row_off, w.p, x_off=w.x_off, x_len=w.X.size, y_len=w.y.size, folds=folds,
+                   path_len=w.path_len, **kw)
+
+    def run(self, X, y, lam, stream=None):
+        """Returns device tensors fold_error [P*K*L], cv_error [P*L], best [P],
+        fold_status [P*K*L] (enqueued on `stream`)."""
+        import torch
+        P, K, L = self.num_problems, self.folds, self.path_len
+        out = dict(fold_error=torch.empty(P * K * L, dtype=torch.float32, device=X.device),
+                   cv_error=torch.empty(P * L, dtype=torch.float32, device=X.device),
+                   best=torch.empty(P, dtype=torch.int32, device=X.device),
+                   fold_status=torch.empty(P * K * L, dtype=torch.int32, device=X.device))
+        check(lib().ladl_cv_run(self._cv, _ptr(X), _ptr(y), _ptr(lam), _ptr(out["fold_error"]),
+                                _ptr(out["cv_error"]), _ptr(out["best"]), _ptr(out["fold_status"]),
+                                _stream(stream)))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_cv", None) and _lib is not None:
+            _lib.ladl_cv_destroy(self._cv)
+            self._cv = None
 
 
 def to_device(w, device="cuda"):

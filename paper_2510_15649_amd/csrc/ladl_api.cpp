@@ -727,3 +727,183 @@ int ladl_plan_describe(ladl_plan_t pl, char *buf, int64_t len)
     return LADL_OK;
 }
 
+
+// --------------------------------------------------------------------------
+// K-fold cross-validation along a lambda path
+// --------------------------------------------------------------------------
+struct ladl_cv_s {
+    int P = 0, K = 0, L = 0, Q = 0;
+    int64_t x_len = 0, y_len = 0;
+    ladl_plan_t inner = nullptr; // one solve per training problem
+    int64_t *d_row_off_b = nullptr, *d_x_off_b = nullptr, *d_tr_off = nullptr, *d_va_off = nullptr;
+    int64_t *d_x_off_tr = nullptr, *d_b_off_tr = nullptr;
+    int32_t *d_p_b = nullptr, *d_tr_rows = nullptr, *d_va_rows = nullptr;
+    float *d_Xtr = nullptr, *d_ytr = nullptr, *d_lamtr = nullptr, *d_b = nullptr, *d_obj = nullptr;
+    float *d_ferr = nullptr;
+    uint32_t *d_act = nullptr;
+    int32_t *d_zr = nullptr, *d_st = nullptr;
+};
+
+static void cv_free(ladl_cv_s *cv)
+{
+    if (cv->inner) ladl_plan_destroy(cv->inner);
+    void *ptrs[] = {cv->d_row_off_b, cv->d_x_off_b, cv->d_tr_off, cv->d_va_off, cv->d_x_off_tr, cv->d_b_off_tr,
+                    cv->d_p_b,       cv->d_tr_rows,  cv->d_va_rows, cv->d_Xtr,   cv->d_ytr,     cv->d_lamtr,
+                    cv->d_b,         cv->d_obj,      cv->d_ferr,    cv->d_act,   cv->d_zr,      cv->d_st};
+    for (void *q : ptrs) (void)hipFree(q);
+    delete cv;
+}
+
+template <typename T>
+static hipError_t dalloc(T **dst, int64_t count)
+{
+    return hipMalloc((void **)dst, sizeof(T) * (size_t)std::max<int64_t>(count, 1));
+}
+
+int ladl_cv_create(ladl_handle_t h, const ladl_cv_layout *lay, const ladl_options *opt, ladl_cv_t *out)
+{
+    if (!out) return fail(LADL_EINVAL, "output pointer is NULL");
+    *out = nullptr;
+    if (!h || !lay || !lay->row_off) return fail(LADL_EINVAL, "handle, layout and row_off are required");
+    const int P = lay->num_problems, K = lay->folds, L = lay->path_len;
+    if (P < 1) return fail(LADL_EINVAL, "num_problems = %d", P);
+    if (K < 2 || K > 64) return fail(LADL_EINVAL, "folds = %d (must be 2..64)", K);
+    if (L < 1 || L > 64) return fail(LADL_EINVAL, "path_len = %d (must be 1..64)", L);
+    std::vector<int64_t> row_off(lay->row_off, lay->row_off + P + 1), x_off(P);
+    std::vector<int32_t> pb(P);
+    if (row_off[0] != 0) return fail(LADL_EINVAL, "row_off[0] must be 0");
+    for (int k = 0; k < P; ++k) {
+        const int64_t n = row_off[k + 1] - row_off[k];
+        if (n < 1) return fail(LADL_EINVAL, "problem %d has %lld rows", k, (long long)n);
+        const int pk = lay->p ? lay->p[k] : lay->p_uniform;
+        if (pk < 1 || pk > PMAX) return fail(LADL_EUNSUPPORTED, "problem %d has p = %d (limit 1..%d)", k, pk, PMAX);
+        const int64_t xo = lay->x_off ? lay->x_off[k] : row_off[k] * (int64_t)lay->p_uniform;
+        if (xo < 0 || xo + n * pk > lay->x_len)
+            return fail(LADL_EINVAL, "problem %d: X block outside x_len %lld", k, (long long)lay->x_len);
+        pb[k] = pk;
+        x_off[k] = xo;
+    }
+    if (row_off[P] > lay->y_len) return fail(LADL_EINVAL, "row_off[%d] exceeds y_len", P);
+    // fold lists
+    const int Q = P * K;
+    std::vector<int64_t> tr_off(Q + 1, 0), va_off(Q + 1, 0), x_off_tr(Q, 0), b_off_tr(Q, 0);
+    std::vector<int32_t> tr_rows, va_rows, p_tr(Q);
+    tr_rows.reserve((size_t)row_off[P] * (K - 1));
+    va_rows.reserve((size_t)row_off[P]);
+    int64_t xacc = 0, bacc = 0;
+    for (int k = 0; k < P; ++k) {
+        const int n = (int)(row_off[k + 1] - row_off[k]);
+        std::vector<int> lab(n);
+        for (int i = 0; i < n; ++i) {
+            lab[i] = lay->fold_of_row ? lay->fold_of_row[row_off[k] + i] : i % K;
+            if (lab[i] < 0 || lab[i] >= K)
+                return fail(LADL_EINVAL, "fold_of_row[%lld] = %d outside 0..%d", (long long)(row_off[k] + i), lab[i],
+                            K - 1);
+        }
+        for (int f = 0; f < K; ++f) {
+            const int q = k * K + f;
+            for (int i = 0; i < n; ++i) (lab[i] == f ? va_rows : tr_rows).push_back(i);
+            tr_off[q + 1] = (int64_t)tr_rows.size();
+            va_off[q + 1] = (int64_t)va_rows.size();
+            const int64_t ntr = tr_off[q + 1] - tr_off[q];
+            if (ntr < 1) return fail(LADL_EINVAL, "fold %d of problem %d leaves no training rows", f, k);
+            p_tr[q] = pb[k];
+            x_off_tr[q] = xacc;
+            b_off_tr[q] = bacc;
+            xacc += ntr * pb[k];
+            bacc += pb[k];
+        }
+    }
+    auto *cv = new (std::nothrow) ladl_cv_s;
+    if (!cv) return fail(LADL_ENOMEM, "host allocation");
+    cv->P = P;
+    cv->K = K;
+    cv->L = L;
+    cv->Q = Q;
+    cv->x_len = xacc;
+    cv->y_len = tr_off[Q];
+    ladl_layout il{};
+    il.num_problems = Q;
+    il.row_off = tr_off.data();
+    il.x_off = x_off_tr.data();
+    il.p = p_tr.data();
+    il.p_uniform = p_tr[0];
+    il.x_len = xacc;
+    il.y_len = tr_off[Q];
+    il.num_solves = Q;
+    il.problem = nullptr;
+    il.path_len = L;
+    il.lambda_hint = nullptr;
+    int rc = ladl_plan_create(h, &il, opt, &cv->inner);
+    if (rc != LADL_OK) {
+        cv->inner = nullptr;
+        std::string d = g_detail;
+        cv_free(cv);
+        return fail(rc, "training problems: %s", d.c_str());
+    }
+    const int64_t nout = (int64_t)Q * L;
+    hipError_t e;
+    if ((e = upload(&cv->d_row_off_b, row_off)) != hipSuccess || (e = upload(&cv->d_x_off_b, x_off)) != hipSuccess ||
+        (e = upload(&cv->d_p_b, pb)) != hipSuccess || (e = upload(&cv->d_tr_off, tr_off)) != hipSuccess ||
+        (e = upload(&cv->d_va_off, va_off)) != hipSuccess || (e = upload(&cv->d_x_off_tr, x_off_tr)) != hipSuccess ||
+        (e = upload(&cv->d_b_off_tr, b_off_tr)) != hipSuccess ||
+        (e = upload(&cv->d_tr_rows, tr_rows.empty() ? std::vector<int32_t>(1, 0) : tr_rows)) != hipSuccess ||
+        (e = upload(&cv->d_va_rows, va_rows.empty() ? std::vector<int32_t>(1, 0) : va_rows)) != hipSuccess ||
+        (e = dalloc(&cv->d_Xtr, xacc)) != hipSuccess || (e = dalloc(&cv->d_ytr, tr_off[Q])) != hipSuccess ||
+        (e = dalloc(&cv->d_lamtr, nout)) != hipSuccess || (e = dalloc(&cv->d_b, bacc * L)) != hipSuccess ||
+        (e = dalloc(&cv->d_obj, nout)) != hipSuccess || (e = dalloc(&cv->d_ferr, nout)) != hipSuccess ||
+        (e = dalloc(&cv->d_act, nout)) != hipSuccess || (e = dalloc(&cv->d_zr, nout * ZPAD)) != hipSuccess ||
+        (e = dalloc(&cv->d_st, nout)) != hipSuccess) {
+        cv_free(cv);
+        return hipfail(e, "cross-validation buffers");
+    }
+    *out = cv;
+    return LADL_OK;
+}
+
+int ladl_cv_destroy(ladl_cv_t cv)
+{
+    if (cv) cv_free(cv);
+    return LADL_OK;
+}
+
+int ladl_cv_run(ladl_cv_t cv, const float *X, const float *y, const float *lam, float *fold_error, float *cv_error,
+                int32_t *best, int32_t *fold_status, void *stream)
+{
+    if (!cv) return fail(LADL_EINVAL, "cross-validation object is NULL");
+    if (!X || !y || !lam || !cv_error || !best) return fail(LADL_EINVAL, "a required device pointer is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    CvArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.X = X;
+    a.y = y;
+    a.lam = lam;
+    a.row_off_b = cv->d_row_off_b;
+    a.x_off_b = cv->d_x_off_b;
+    a.p_b = cv->d_p_b;
+    a.num_base = cv->P;
+    a.folds = cv->K;
+    a.path_len = cv->L;
+    a.num_train = cv->Q;
+    a.tr_rows = cv->d_tr_rows;
+    a.va_rows = cv->d_va_rows;
+    a.tr_off = cv->d_tr_off;
+    a.va_off = cv->d_va_off;
+    a.x_off_tr = cv->d_x_off_tr;
+    a.b_off_tr = cv->d_b_off_tr;
+    a.Xtr = cv->d_Xtr;
+    a.ytr = cv->d_ytr;
+    a.lam_tr = cv->d_lamtr;
+    a.b = cv->d_b;
+    a.fold_err = fold_error ? fold_error : cv->d_ferr;
+    a.cv_err = cv_error;
+    a.best = best;
+    hipError_t e = launch_cv_gather(a, s);
+    if (e != hipSuccess) return hipfail(e, "cross-validation gather");
+    int rc = ladl_solve_f32(cv->inner, cv->d_Xtr, cv->d_ytr, cv->d_lamtr, nullptr, cv->d_b, cv->d_obj, cv->d_act,
+                            cv->d_zr, fold_status ? fold_status : cv->d_st, nullptr, stream);
+    if (rc != LADL_OK) return rc;
+    e = launch_cv_score(a, s);
+    if (e != hipSuccess) return hipfail(e, "cross-validation scoring");
+    return LADL_OK;
+}

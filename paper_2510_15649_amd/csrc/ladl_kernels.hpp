@@ -44,6 +44,22 @@ struct BackwardArgs {
     float *bw;            // 32 floats per solve: w of the vertex solve (NaN: none)
 };
 
+// K-fold cross-validation: training problem q = k*folds + f holds the rows
+// of base problem k outside fold f (local indices tr_rows[tr_off[q] ..
+// tr_off[q+1])); the rows in the fold are va_rows[va_off[q] .. va_off[q+1]).
+struct CvArgs {
+    const float *X, *y, *lam;            // base problems, lambda [P * path_len]
+    const int64_t *row_off_b, *x_off_b;  // base layout
+    const int32_t *p_b;
+    int32_t num_base, folds, path_len, num_train;
+    const int32_t *tr_rows, *va_rows;
+    const int64_t *tr_off, *va_off, *x_off_tr, *b_off_tr;
+    float *Xtr, *ytr, *lam_tr;           // packed training problems
+    const float *b;                      // training solves' b (all steps)
+    float *fold_err, *cv_err;
+    int32_t *best;
+};
+
 // host-side launchers (defined in ladl_kernels.hip)
 // wave kernel: R = row slots per lane (1..32); xg = X held in a per-wave
 // global workspace instead of LDS (required for R = 32)
@@ -55,5 +71,7 @@ hipError_t launch_wave(int R, bool xg, const SolveArgs &a, int grid, hipStream_t
 hipError_t launch_plain(const SolveArgs &a, int NM, int64_t nthreads, hipStream_t s);
 int64_t plain_scratch_floats(int NM, int64_t nthreads);
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);
+hipError_t launch_cv_gather(const CvArgs &a, hipStream_t s);
+hipError_t launch_cv_score(const CvArgs &a, hipStream_t s);
 
 } // namespace ladl

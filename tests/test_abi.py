@@ -36,6 +36,9 @@ def test_host_only_entry_points():
     assert lib.ladl_plan_create(None, None, None, None) == L.EINVAL
     assert lib.ladl_solve_f32(*([None] * 12)) == L.EINVAL
     assert b"NULL" in lib.ladl_last_error_detail()
+    assert lib.ladl_cv_create(None, None, None, None) == L.EINVAL
+    assert lib.ladl_cv_run(*([None] * 9)) == L.EINVAL
+    assert lib.ladl_cv_destroy(None) == L.OK
 
 
 def test_no_packed_fp32_or_scalar_stores_in_device_code():
@@ -44,13 +47,16 @@ def test_no_packed_fp32_or_scalar_stores_in_device_code():
     emits for the kernels of this repository)."""
     import subprocess
     import tempfile
-    src = os.path.join(ROOT, "paper_2510_15649_amd", "csrc", "ladl_solve_wave.hip")
-    with tempfile.TemporaryDirectory() as td:
-        out = os.path.join(td, "k.s")
-        subprocess.check_call(["/opt/rocm/bin/hipcc", "-O3", "-std=c++17", "--offload-arch=gfx950", "-x", "hip",
-                               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only",
-                               "-S", src, "-I", os.path.join(ROOT, "include"), "-o", out],
-                              stderr=subprocess.DEVNULL)
-        asm = open(out).read()
-    assert "v_pk_fma_f32" not in asm and "v_pk_add_f32" not in asm and "v_pk_mul_f32" not in asm
-    assert not re.search(r"\bs_(store|atomic|buffer_store|dcache_wb)", asm)
+    csrc = os.path.join(ROOT, "paper_2510_15649_amd", "csrc")
+    srcs = sorted(f for f in os.listdir(csrc) if f.endswith(".hip"))
+    assert len(srcs) >= 3
+    for name in srcs:
+        with tempfile.TemporaryDirectory() as td:
+            out = os.path.join(td, "k.s")
+            subprocess.check_call(["/opt/rocm/bin/hipcc", "-O3", "-std=c++17", "--offload-arch=gfx950", "-x", "hip",
+                                   "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only",
+                                   "-S", os.path.join(csrc, name), "-I", os.path.join(ROOT, "include"), "-o", out],
+                                  stderr=subprocess.DEVNULL)
+            asm = open(out).read()
+        assert "v_pk_fma_f32" not in asm and "v_pk_add_f32" not in asm and "v_pk_mul_f32" not in asm, name
+        assert not re.search(r"\bs_(store|atomic|buffer_store|dcache_wb)", asm), name
