@@ -216,6 +216,27 @@ const char *ladl_error_string(int code);
 const char *ladl_last_error_detail(void);
 
 /*
+ * Exact solve by vertex enumeration (Section 3.2): every choice of p of the
+ * n + p hyperplanes {x_i.b = y_i} and {b_j = 0} that meet in one point is
+ * evaluated, and the point of least f is returned (the global minimum: f is
+ * piecewise linear and attains its minimum at a vertex).  For the paper's
+ * evaluation sizes: every solve of the plan needs p <= 8, n + p <= 64 and
+ * C(n+p, p) <= 2^31, else LADL_EUNSUPPORTED.  Each (solve, path step) is
+ * independent (no warm start).  Vertex systems and f in fp64; ties go to
+ * the first vertex in lexicographic order of hyperplane indices (rows
+ * 0..n-1, then axes n..n+p-1).
+ *   b         device, packed as for ladl_solve_f32 (output)
+ *   obj       device [num_solves*path_len]: the minimum f, NaN if no
+ *             vertex exists (output)
+ *   vertices  device int64 [num_solves*path_len] or NULL: non-singular
+ *             vertices evaluated (output)
+ * The plan's queue order and schedule are not used; the first call on a
+ * plan uploads a per-p order of its solves.
+ */
+int ladl_brute_force_f32(ladl_plan_t plan, const float *X, const float *y, const float *lambda, float *b,
+                         float *obj, int64_t *vertices, void *stream);
+
+/*
  * K-fold cross-validation along a lambda path, all on the device: the
  * paper's interactive use of several regularisation settings solved while
  * cross-validating (Section 5).  For every base problem k and fold f, the

@@ -29,7 +29,7 @@ EXPORTED = ["ladl_create", "ladl_destroy", "ladl_default_options", "ladl_plan_cr
             "ladl_plan_b_len", "ladl_solve_f32", "ladl_solve_plain_f32", "ladl_backward_f32",
             "ladl_graph_create", "ladl_graph_launch", "ladl_graph_destroy", "ladl_autotune",
             "ladl_plan_describe", "ladl_error_string", "ladl_last_error_detail", "ladl_cv_create",
-            "ladl_cv_destroy", "ladl_cv_run"]
+            "ladl_cv_destroy", "ladl_cv_run", "ladl_brute_force_f32"]
 
 
 class Options(C.Structure):
@@ -92,6 +92,7 @@ def lib() -> C.CDLL:
     L.ladl_graph_destroy.argtypes = [vp]
     L.ladl_autotune.argtypes = [vp] + [vp] * 9
     L.ladl_plan_describe.argtypes = [vp, C.c_char_p, i64]
+    L.ladl_brute_force_f32.argtypes = [vp] * 8
     L.ladl_cv_create.argtypes = [vp, C.POINTER(CVLayout), C.POINTER(Options), C.POINTER(vp)]
     L.ladl_cv_destroy.argtypes = [vp]
     L.ladl_cv_run.argtypes = [vp] + [vp] * 7 + [vp]
@@ -102,7 +103,7 @@ def lib() -> C.CDLL:
     for name in ["ladl_create", "ladl_destroy", "ladl_plan_create", "ladl_plan_destroy", "ladl_solve_f32",
                  "ladl_solve_plain_f32", "ladl_backward_f32", "ladl_graph_create", "ladl_graph_launch",
                  "ladl_graph_destroy", "ladl_autotune", "ladl_plan_describe", "ladl_cv_create", "ladl_cv_destroy",
-                 "ladl_cv_run"]:
+                 "ladl_cv_run", "ladl_brute_force_f32"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -261,6 +262,18 @@ class Plan:
         """The same solve with one GPU thread per solve (baseline kernel)."""
         out = out or self.alloc_outputs(X.device, iters)
         return self._call(lib().ladl_solve_plain_f32, X, y, lam, b_init, out, stream)
+
+    def brute_force(self, X, y, lam, stream=None):
+        """Exact solve by vertex enumeration on the device (small problems:
+        p <= 8, n + p <= 64).  Returns device tensors b, obj, vertices."""
+        import torch
+        n_out = self.num_solves * self.path_len
+        out = dict(b=torch.empty(self.b_len, dtype=torch.float32, device=X.device),
+                   obj=torch.empty(n_out, dtype=torch.float32, device=X.device),
+                   vertices=torch.empty(n_out, dtype=torch.int64, device=X.device))
+        check(lib().ladl_brute_force_f32(self._plan, _ptr(X), _ptr(y), _ptr(lam), _ptr(out["b"]), _ptr(out["obj"]),
+                                         _ptr(out["vertices"]), _stream(stream)))
+        return out
 
     def backward(self, X, out, grad_b, step: int = -1, grad_y=None, grad_X=None, stream=None):
         import torch

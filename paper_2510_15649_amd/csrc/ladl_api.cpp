@@ -80,6 +80,8 @@ struct ladl_plan_s {
     float *d_wws = nullptr;      // wave kernel workspace (buckets with X outside LDS)
     int64_t wws_floats = 0;
     float *d_bw = nullptr;       // backward: 32 floats per solve (plans with each problem once)
+    int32_t *d_bf_order = nullptr; // vertex enumeration: solves grouped by p (built on first use)
+    std::vector<std::pair<int, int>> bf_buckets; // (p, count) in d_bf_order order
     // buckets run concurrently on streams forked from the caller's stream
     std::vector<hipStream_t> bstreams;
     std::vector<hipEvent_t> ev_join;
@@ -187,6 +189,7 @@ static void plan_free_device(ladl_plan_s *pl)
     (void)hipFree(pl->d_gws);
     (void)hipFree(pl->d_wws);
     (void)hipFree(pl->d_bw);
+    (void)hipFree(pl->d_bf_order);
     for (hipStream_t st : pl->bstreams) (void)hipStreamDestroy(st);
     for (hipEvent_t ev : pl->ev_join) (void)hipEventDestroy(ev);
     if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
@@ -905,5 +908,68 @@ int ladl_cv_run(ladl_cv_t cv, const float *X, const float *y, const float *lam, 
     if (rc != LADL_OK) return rc;
     e = launch_cv_score(a, s);
     if (e != hipSuccess) return hipfail(e, "cross-validation scoring");
+    return LADL_OK;
+}
+
+// --------------------------------------------------------------------------
+// Exact solve by vertex enumeration (small problems)
+// --------------------------------------------------------------------------
+int ladl_brute_force_f32(ladl_plan_t pl, const float *X, const float *y, const float *lam, float *b, float *obj,
+                         int64_t *vertices, void *stream)
+{
+    if (!pl) return fail(LADL_EINVAL, "plan is NULL");
+    if (!X || !y || !lam || !b || !obj) return fail(LADL_EINVAL, "a required device pointer is NULL");
+    for (int s = 0; s < pl->S; ++s) {
+        const int k = pl->problem[s];
+        const int n = (int)(pl->row_off[k + 1] - pl->row_off[k]), p = pl->p[k];
+        if (p > 8 || n + p > 64)
+            return fail(LADL_EUNSUPPORTED, "solve %d: n = %d, p = %d (vertex enumeration needs p <= 8, n + p <= 64)",
+                        s, n, p);
+        double c = 1.0;
+        for (int j = 1; j <= p; ++j) c = c * (n + j) / j;
+        if (c > 2147483647.0)
+            return fail(LADL_EUNSUPPORTED, "solve %d: C(%d, %d) vertices exceed 2^31", s, n + p, p);
+    }
+    if (!pl->d_bf_order && pl->S > 0) {
+        std::vector<int32_t> ord;
+        ord.reserve(pl->S);
+        pl->bf_buckets.clear();
+        for (int p = 1; p <= 8; ++p) {
+            int cnt = 0;
+            for (int s = 0; s < pl->S; ++s)
+                if (pl->p[pl->problem[s]] == p) {
+                    ord.push_back(s);
+                    ++cnt;
+                }
+            if (cnt) pl->bf_buckets.push_back({p, cnt});
+        }
+        hipError_t e = upload(&pl->d_bf_order, ord);
+        if (e != hipSuccess) {
+            pl->d_bf_order = nullptr;
+            return hipfail(e, "vertex enumeration order");
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int off = 0;
+    for (const auto &bk : pl->bf_buckets) {
+        BruteArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.X = X;
+        a.y = y;
+        a.lam = lam;
+        a.row_off = pl->d_row_off;
+        a.x_off = pl->d_x_off;
+        a.b_off = pl->d_b_off;
+        a.problem = pl->d_problem;
+        a.order = pl->d_bf_order + off;
+        a.count = bk.second;
+        a.path_len = pl->L;
+        a.b_out = b;
+        a.obj_out = obj;
+        a.vert_out = vertices;
+        hipError_t e = launch_brute(bk.first, a, st);
+        if (e != hipSuccess) return hipfail(e, "vertex enumeration launch");
+        off += bk.second;
+    }
     return LADL_OK;
 }

@@ -60,6 +60,16 @@ struct CvArgs {
     int32_t *best;
 };
 
+// vertex enumeration: the solves in order[0 .. count) all have the same p
+struct BruteArgs {
+    const float *X, *y, *lam;
+    const int64_t *row_off, *x_off, *b_off;
+    const int32_t *problem, *order;
+    int32_t count, path_len;
+    float *b_out, *obj_out;
+    int64_t *vert_out; // non-singular vertices examined per output, or null
+};
+
 // host-side launchers (defined in ladl_kernels.hip)
 // wave kernel: R = row slots per lane (1..32); xg = X held in a per-wave
 // global workspace instead of LDS (required for R = 32)
@@ -73,5 +83,6 @@ int64_t plain_scratch_floats(int NM, int64_t nthreads);
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t launch_cv_gather(const CvArgs &a, hipStream_t s);
 hipError_t launch_cv_score(const CvArgs &a, hipStream_t s);
+hipError_t launch_brute(int p, const BruteArgs &a, hipStream_t s);
 
 } // namespace ladl

@@ -259,5 +259,30 @@ def config4(replica: int = 0, problems: Optional[Sequence[int]] = None, num_prob
     return w
 
 
+def paper_sizes(replica: int = 0, num_problems: int = 4096, n_range=(10, 30), p_range=(1, 5),
+                lams=(0.1, 1.0, 10.0)) -> Workload:
+    """Problems of the sizes the paper evaluates (Section 4: 10 to 30 data
+    points, one to five explanatory variables), each solved at every lambda
+    in `lams` as independent solves: X ~ N(0,1), about half the
+    coefficients non-zero ~U[-3,3], Laplace(0,1) noise with 10% outliers
+    N(0, 10^2).  Stands in for the paper's scikit-learn generated data."""
+    seed = BASE_SEED + 5000 + replica
+    blocks, ps = [], []
+    for k in range(num_problems):
+        g = _rng(seed, k)
+        n = int(g.integers(n_range[0], n_range[1] + 1))
+        p = int(g.integers(p_range[0], p_range[1] + 1))
+        X = g.standard_normal((n, p))
+        bt = _sparse_beta(g, p, max(1, (p + 1) // 2))
+        e = _outliers(g, g.laplace(0.0, 1.0, size=n), 0.1, 10.0)
+        blocks.append((X, X @ bt + e))
+        ps.append(p)
+    L = len(lams)
+    problem = np.repeat(np.arange(num_problems), L)
+    lam = np.tile(np.asarray(lams, dtype=np.float64), num_problems)
+    return _pack(f"paper sizes: {num_problems} problems n~U[{n_range[0]},{n_range[1]}] "
+                 f"p~U[{p_range[0]},{p_range[1]}] x {L} lambdas", blocks, ps, problem, lam, 1)
+
+
 def make(c: int, **kw) -> Workload:
     return [config0, config1, config2, config3, config4][c](**kw)
