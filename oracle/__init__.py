@@ -292,3 +292,28 @@ def cv(X, y, lams, folds: int, fold_of_row=None, **opts):
             uniq[f, t] = bool(info["unique"]) and info["margin_uc"] >= 1e-3 and info["margin_r"] >= 1e-6
     curve = err.sum(axis=0)
     return dict(err=err, unique=uniq, cv=curve, best=int(np.argmin(curve)), b=bs)
+
+
+def selection_frequency(active, status, group, num_groups: int, path_len: int, ok_status=(0, 1)):
+    """Subset-stability statistics (the paper's aim of telling informative
+    from non-informative variables by fitting many row subsets, Section 1
+    and Section 5), by plain counting: for group g, path step t and feature
+    j, the fraction of the solves s in g (with an accepted status) whose
+    coefficient j is non-zero, read from bit j of active[s*path_len + t].
+    Returns (freq [G, L, 32], counts [G, L])."""
+    active = np.asarray(active, dtype=np.uint64).reshape(-1, path_len)
+    status = np.asarray(status).reshape(-1, path_len)
+    group = np.asarray(group)
+    hits = np.zeros((num_groups, path_len, 32))
+    cnt = np.zeros((num_groups, path_len))
+    for s in range(active.shape[0]):
+        for t in range(path_len):
+            if int(status[s, t]) not in ok_status:
+                continue
+            g = int(group[s])
+            cnt[g, t] += 1
+            for j in range(32):
+                if (int(active[s, t]) >> j) & 1:
+                    hits[g, t, j] += 1
+    freq = np.divide(hits, cnt[:, :, None], out=np.zeros_like(hits), where=cnt[:, :, None] > 0)
+    return freq, cnt
