@@ -14,6 +14,7 @@ import json
 import os
 import re
 import sys
+import time
 
 import numpy as np
 
@@ -207,6 +208,53 @@ def measure_cv(L, torch, folds=5, steps=3, sample=4):
             "training_solves": int(st.size)}
 
 
+def measure_brute(L, torch, steps=3, sample=16):
+    """Vertex enumeration (Section 3.2) of 4096 problems of the paper's
+    evaluation sizes at 3 lambdas; fp64 ALU roofline; parity of the minimum
+    on a sample against the oracle's enumeration; the oracle's enumeration
+    on one host thread for the same sample."""
+    import oracle as O
+    from math import comb
+    from paper_2510_15649_amd import workloads as W
+    w = W.paper_sizes()
+    log(f"vertex enumeration: {w.name}")
+    plan = L.Plan.for_workload(w)
+    d = L.to_device(w)
+    stream = torch.cuda.current_stream()
+    out = plan.brute_force(d["X"], d["y"], d["lam"], stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        out = plan.brute_force(d["X"], d["y"], d["lam"], stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ns = np.diff(w.row_off)[w.problem]
+    ps = w.p[w.problem]
+    cand = np.array([comb(int(n) + int(p), int(p)) for n, p in zip(ns, ps)], dtype=np.float64)
+    # per candidate: LU 2p^3/3, two triangular solves 2p^2, residuals 2np, |r| sums n
+    flops = float(np.sum(cand * (2.0 * ps ** 3 / 3 + 2.0 * ps ** 2 + 2.0 * ns * ps + ns)))
+    achieved = flops / (ms / 1e3) / 1e12
+    obj = out["obj"].cpu().numpy()
+    rng = np.random.default_rng(5)
+    pick = np.sort(rng.choice(w.num_solves, size=sample, replace=False))
+    worst, t_cpu = 0.0, 0.0
+    for s_ in pick:
+        Xk, yk = w.block(int(w.problem[s_]))
+        t0 = time.perf_counter()
+        fo, _, _ = O.brute_force(Xk, yk, float(w.lam[s_]))
+        t_cpu += time.perf_counter() - t0
+        worst = max(worst, abs(float(obj[s_]) - fo) / max(1.0, fo))
+    cpu_rate = sample / t_cpu * (cand.mean() / cand[pick].mean())
+    return {"workload": f"vertex enumeration, {w.name}", "ms_per_step": ms,
+            "solves_per_s": w.num_solves / (ms / 1e3), "candidate_vertices_per_step": float(cand.sum()),
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s (fp64)",
+                         "frac": achieved / 78.6},
+            "parity_sample": sample, "max_rel_f": worst, "parity_ok": worst <= 1e-6,
+            "oracle_1_thread_solves_per_s": cpu_rate}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,6 +363,7 @@ def main():
                 backward = backward or bw
             secondary.append(entry)
         secondary.append(measure_cv(L, torch))
+        secondary.append(measure_brute(L, torch))
 
     line = {
         "metric": METRIC,

@@ -237,6 +237,27 @@ int ladl_brute_force_f32(ladl_plan_t plan, const float *X, const float *y, const
                          float *obj, int64_t *vertices, void *stream);
 
 /*
+ * Subset-stability statistics over a plan's outputs: the paper's end goal
+ * of telling informative from non-informative variables by fitting many
+ * row subsets (Sections 1 and 5).  Solve s belongs to group group[s]
+ * (device int32 [num_solves], or NULL: all in group 0).  For group g, path
+ * step t and feature j:
+ *   counts[(g*path_len + t)*33 + j]  solves of g whose b_j at step t is
+ *                                    non-zero (bit j of active), j < 32
+ *   counts[(g*path_len + t)*33 + 32] solves of g counted (status
+ *                                    LADL_CERTIFIED or LADL_NONUNIQUE)
+ *   freq[(g*path_len + t)*32 + j]    their ratio (0 when none counted)
+ * active, status: the outputs of a solve with this plan (device).  counts
+ * (int32 [num_groups*path_len*33]) is the caller's and is overwritten.
+ * bad_group (device int32 [1]) is set to 1 if a group id lies outside
+ * [0, num_groups) (that solve is skipped), else 0.  Exact integer counts:
+ * the result does not depend on the order of the solves.
+ */
+int ladl_selection_frequency(ladl_plan_t plan, const uint32_t *active, const int32_t *status,
+                             const int32_t *group, int32_t num_groups, int32_t *counts, float *freq,
+                             int32_t *bad_group, void *stream);
+
+/*
  * K-fold cross-validation along a lambda path, all on the device: the
  * paper's interactive use of several regularisation settings solved while
  * cross-validating (Section 5).  For every base problem k and fold f, the

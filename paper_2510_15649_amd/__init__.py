@@ -29,7 +29,7 @@ EXPORTED = ["ladl_create", "ladl_destroy", "ladl_default_options", "ladl_plan_cr
             "ladl_plan_b_len", "ladl_solve_f32", "ladl_solve_plain_f32", "ladl_backward_f32",
             "ladl_graph_create", "ladl_graph_launch", "ladl_graph_destroy", "ladl_autotune",
             "ladl_plan_describe", "ladl_error_string", "ladl_last_error_detail", "ladl_cv_create",
-            "ladl_cv_destroy", "ladl_cv_run", "ladl_brute_force_f32"]
+            "ladl_cv_destroy", "ladl_cv_run", "ladl_brute_force_f32", "ladl_selection_frequency"]
 
 
 class Options(C.Structure):
@@ -93,6 +93,7 @@ def lib() -> C.CDLL:
     L.ladl_autotune.argtypes = [vp] + [vp] * 9
     L.ladl_plan_describe.argtypes = [vp, C.c_char_p, i64]
     L.ladl_brute_force_f32.argtypes = [vp] * 8
+    L.ladl_selection_frequency.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp]
     L.ladl_cv_create.argtypes = [vp, C.POINTER(CVLayout), C.POINTER(Options), C.POINTER(vp)]
     L.ladl_cv_destroy.argtypes = [vp]
     L.ladl_cv_run.argtypes = [vp] + [vp] * 7 + [vp]
@@ -103,7 +104,7 @@ def lib() -> C.CDLL:
     for name in ["ladl_create", "ladl_destroy", "ladl_plan_create", "ladl_plan_destroy", "ladl_solve_f32",
                  "ladl_solve_plain_f32", "ladl_backward_f32", "ladl_graph_create", "ladl_graph_launch",
                  "ladl_graph_destroy", "ladl_autotune", "ladl_plan_describe", "ladl_cv_create", "ladl_cv_destroy",
-                 "ladl_cv_run", "ladl_brute_force_f32"]:
+                 "ladl_cv_run", "ladl_brute_force_f32", "ladl_selection_frequency"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -262,6 +263,24 @@ class Plan:
         """The same solve with one GPU thread per solve (baseline kernel)."""
         out = out or self.alloc_outputs(X.device, iters)
         return self._call(lib().ladl_solve_plain_f32, X, y, lam, b_init, out, stream)
+
+    def selection_frequency(self, out, group=None, num_groups: int = 1, stream=None):
+        """Per group, path step and feature: the fraction of accepted solves
+        with b_j != 0 (subset stability).  `out` holds a solve's outputs;
+        group: device int32 [num_solves] or None.  Returns device tensors
+        freq [G, L, 32], counts [G, L, 33] and bad_group [1]."""
+        import torch
+        dev = out["active"].device
+        G, Lp = int(num_groups), self.path_len
+        res = dict(freq=torch.empty(G * Lp * 32, dtype=torch.float32, device=dev),
+                   counts=torch.empty(G * Lp * 33, dtype=torch.int32, device=dev),
+                   bad_group=torch.empty(1, dtype=torch.int32, device=dev))
+        check(lib().ladl_selection_frequency(self._plan, _ptr(out["active"]), _ptr(out["status"]), _ptr(group), G,
+                                             _ptr(res["counts"]), _ptr(res["freq"]), _ptr(res["bad_group"]),
+                                             _stream(stream)))
+        res["freq"] = res["freq"].view(G, Lp, 32)
+        res["counts"] = res["counts"].view(G, Lp, 33)
+        return res
 
     def brute_force(self, X, y, lam, stream=None):
         """Exact solve by vertex enumeration on the device (small problems:

@@ -973,3 +973,19 @@ int ladl_brute_force_f32(ladl_plan_t pl, const float *X, const float *y, const f
     }
     return LADL_OK;
 }
+
+// --------------------------------------------------------------------------
+// Subset-stability statistics over a plan's outputs
+// --------------------------------------------------------------------------
+int ladl_selection_frequency(ladl_plan_t pl, const uint32_t *active, const int32_t *status, const int32_t *group,
+                             int32_t num_groups, int32_t *counts, float *freq, int32_t *bad_group, void *stream)
+{
+    if (!pl) return fail(LADL_EINVAL, "plan is NULL");
+    if (!active || !status || !counts || !freq || !bad_group)
+        return fail(LADL_EINVAL, "a required device pointer is NULL");
+    if (num_groups < 1) return fail(LADL_EINVAL, "num_groups = %d", num_groups);
+    hipError_t e = launch_selection_frequency(active, status, group, pl->S, pl->L, num_groups, counts, freq,
+                                              bad_group, (hipStream_t)stream);
+    if (e != hipSuccess) return hipfail(e, "selection frequency launch");
+    return LADL_OK;
+}

@@ -99,4 +99,69 @@ hipError_t launch_cv_score(const CvArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// --------------------------------------------------------------------------
+// Subset-stability statistics: for group g, path step t, feature j, the
+// fraction of the group's solves (status certified or non-unique) whose b_j
+// is non-zero.  Integer counts by atomics, so the result does not depend on
+// the order of the solves.  counts holds G * L * 33 ints: 32 feature hits
+// and the number of accepted solves.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sel_zero(int32_t *c, int64_t n, int32_t *bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = 0;
+    if (i == 0) *bad = 0;
+}
+
+__global__ __launch_bounds__(256) void k_sel_count(const uint32_t *active, const int32_t *status,
+                                                   const int32_t *group, int32_t S, int32_t L, int32_t G,
+                                                   int32_t *c, int32_t *bad)
+{
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; // output (s, t)
+    if (o >= (int64_t)S * L) return;
+    const int s = (int)(o / L), t = (int)(o - (int64_t)s * L);
+    const int g = group ? group[s] : 0;
+    if (g < 0 || g >= G) {
+        atomicOr(bad, 1);
+        return;
+    }
+    const int st = status[o];
+    if (st != ST_CERTIFIED && st != ST_NONUNIQUE) return;
+    int32_t *cg = c + ((int64_t)g * L + t) * 33;
+    uint32_t m = active[o];
+    while (m) {
+        const int j = __builtin_ctz(m);
+        m &= m - 1;
+        atomicAdd(cg + j, 1);
+    }
+    atomicAdd(cg + 32, 1);
+}
+
+__global__ __launch_bounds__(256) void k_sel_norm(const int32_t *c, int64_t GL, float *freq)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; // (g, t, j)
+    if (i >= GL * 32) return;
+    const int64_t gt = i / 32;
+    const int j = (int)(i - gt * 32);
+    const int32_t n = c[gt * 33 + 32];
+    freq[i] = n > 0 ? (float)((double)c[gt * 33 + j] / (double)n) : 0.f;
+}
+
+hipError_t launch_selection_frequency(const uint32_t *active, const int32_t *status, const int32_t *group,
+                                      int32_t num_solves, int32_t path_len, int32_t num_groups, int32_t *counts,
+                                      float *freq, int32_t *bad_group, hipStream_t s)
+{
+    const int64_t GL = (int64_t)num_groups * path_len;
+    const int64_t nc = GL * 33, no = (int64_t)num_solves * path_len;
+    hipLaunchKernelGGL(k_sel_zero, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, counts, nc, bad_group);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (no > 0)
+        hipLaunchKernelGGL(k_sel_count, dim3((unsigned)((no + 255) / 256)), dim3(256), 0, s, active, status, group,
+                           num_solves, path_len, num_groups, counts, bad_group);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sel_norm, dim3((unsigned)((GL * 32 + 255) / 256)), dim3(256), 0, s, counts, GL, freq);
+    return hipGetLastError();
+}
+
 } // namespace ladl

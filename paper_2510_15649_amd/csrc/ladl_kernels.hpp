@@ -84,5 +84,8 @@ hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t launch_cv_gather(const CvArgs &a, hipStream_t s);
 hipError_t launch_cv_score(const CvArgs &a, hipStream_t s);
 hipError_t launch_brute(int p, const BruteArgs &a, hipStream_t s);
+hipError_t launch_selection_frequency(const uint32_t *active, const int32_t *status, const int32_t *group,
+                                      int32_t num_solves, int32_t path_len, int32_t num_groups, int32_t *counts,
+                                      float *freq, int32_t *bad_group, hipStream_t s);
 
 } // namespace ladl
