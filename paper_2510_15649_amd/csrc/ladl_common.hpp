@@ -24,6 +24,7 @@ constexpr float TOL_CA = 1e-8f;
 constexpr float MARGIN_U = 1e-3f, MARGIN_C = 1e-3f, MARGIN_R = 1e-5f;
 
 constexpr int ALD = 33; // leading dimension of the vertex matrix
+constexpr int REFINE_MAX = 8; // refinement steps of the vertex and dual solves
 
 #define LADL_INL __device__ __attribute__((always_inline)) inline
 

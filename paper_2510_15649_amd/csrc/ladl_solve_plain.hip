@@ -337,8 +337,9 @@ __device__ bool pt_vertex_eval(PT &t, int s, float &f)
     float v[PMAX], e[PMAX];
     for (int q = 0; q < s; ++q) v[q] = t.y[t.zs[q]];
     pt_solve(t, s, v);
-    // mixed-precision refinement: residual in fp64
-    for (int it = 0; it < 3; ++it) {
+    // mixed-precision refinement: residual in fp64, until the correction is
+    // at rounding level
+    for (int it = 0; it < REFINE_MAX; ++it) {
         float cm = 0.f, xm = 0.f;
         for (int q = 0; q < s; ++q) {
             double acc = (double)t.y[t.zs[q]];
@@ -384,7 +385,7 @@ __device__ bool pt_certificate(PT &t, int s, float *u, float *c, bool &unique)
         u[q] = (float)rhs[q];
     }
     pt_solve_t(t, s, u);
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < REFINE_MAX; ++it) {
         float du[PMAX];
         for (int c = 0; c < s; ++c) {
             double acc = rhs[c];
@@ -392,7 +393,13 @@ __device__ bool pt_certificate(PT &t, int s, float *u, float *c, bool &unique)
             du[c] = (float)acc;
         }
         pt_solve_t(t, s, du);
-        for (int c = 0; c < s; ++c) u[c] += du[c];
+        float cm = 0.f, um = 1.f;
+        for (int c = 0; c < s; ++c) {
+            u[c] += du[c];
+            cm = fmaxf(cm, fabsf(du[c]));
+            um = fmaxf(um, fabsf(u[c]));
+        }
+        if (cm <= 1e-7f * um) break;
     }
     float umax = 0.f;
     for (int q = 0; q < s; ++q) umax = fmaxf(umax, fabsf(u[q]));

@@ -708,8 +708,10 @@ LADL_INL bool vertex_eval(Wave<R, XG> &w, float (&rv)[R], uint32_t zbits, int s,
     if (!lu_factor(w.A, w.piv, s)) return false;
     const float yz = (l < s) ? w.ys[zl] : 0.f;
     float xs = lu_solve(w.A, w.piv, s, yz);
-    // mixed-precision refinement: residual y_Z - X_{Z,S} b_S in fp64
-    for (int it = 0; it < 3; ++it) {
+    // mixed-precision refinement: residual y_Z - X_{Z,S} b_S in fp64, until
+    // the correction is at rounding level (each step gains a factor of about
+    // cond(X_{Z,S}) * 2^-24, so ill-conditioned vertices take more steps)
+    for (int it = 0; it < REFINE_MAX; ++it) {
         double acc = (double)yz;
         for (int c = 0; c < s; ++c) {
             const float xc = rdlane(xs, c);
@@ -768,14 +770,17 @@ LADL_INL bool certificate(Wave<R, XG> &w, const float (&rv)[R], uint32_t zbits, 
     double rhs = 0.0;
     if (l < s) rhs = (double)w.lam * (double)sgnf(w.vt[jl]) - w.gd[jl];
     u = lu_solve_t(w.A, w.piv, s, (float)rhs);
-    // refinement: residual rhs - X_{Z,S}^T u in fp64
-    for (int it = 0; it < 2; ++it) {
+    // refinement: residual rhs - X_{Z,S}^T u in fp64, until the correction
+    // is at rounding level (the certificate compares |u_i| with 1 to 2e-5)
+    for (int it = 0; it < REFINE_MAX; ++it) {
         double acc = rhs;
         for (int q = 0; q < s; ++q) {
             const float uq = rdlane(u, q);
             if (l < s) acc -= (double)w.A0[q * a0ld + l] * (double)uq;
         }
-        u += lu_solve_t(w.A, w.piv, s, (l < s) ? (float)acc : 0.f);
+        const float corr = lu_solve_t(w.A, w.piv, s, (l < s) ? (float)acc : 0.f);
+        u += corr;
+        if (wmax(fabsf(corr)) <= 1e-7f * fmaxf(1.f, wmax(fabsf(u)))) break;
     }
     double cj = g;
     for (int q = 0; q < s; ++q) {
