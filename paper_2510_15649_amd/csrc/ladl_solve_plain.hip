@@ -360,10 +360,11 @@ __device__ bool pt_vertex_eval(PT &t, int s, float &f)
         if (!__builtin_isfinite(bc)) return false;
         t.bt[t.ss[c]] = bc;
     }
+    // residuals in fp64 (stored as fp32): the certificate reads their signs
     for (int i = 0; i < t.n; ++i) {
-        float r = t.y[i];
-        for (int c = 0; c < s; ++c) r = fmaf(-t.x(i, t.ss[c]), t.bt[t.ss[c]], r);
-        t.rv[i] = t.zf[i] ? 0.f : r;
+        double r = (double)t.y[i];
+        for (int c = 0; c < s; ++c) r = fma(-(double)t.x(i, t.ss[c]), (double)t.bt[t.ss[c]], r);
+        t.rv[i] = t.zf[i] ? 0.f : (float)r;
     }
     f = pt_objective(t, t.rv, t.bt);
     return true;

@@ -726,14 +726,19 @@ LADL_INL bool vertex_eval(Wave<R, XG> &w, float (&rv)[R], uint32_t zbits, int s,
     __syncthreads();
     if (l < s) w.vt[jl] = xs;
     __syncthreads();
+    // residuals in fp64 (stored as fp32): the certificate reads their signs,
+    // and a row a few ulps of y from its hyperplane must keep its true sign
+    double racc[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) rv[k] = w.ys[64 * k + l];
+    for (int k = 0; k < R; ++k) racc[k] = (double)w.ys[64 * k + l];
     for (int c = 0; c < s; ++c) {
         const int jc = rdlane(jl, c);
-        const float bc = rdlane(xs, c);
+        const double bc = (double)rdlane(xs, c);
 #pragma unroll
-        for (int k = 0; k < R; ++k) rv[k] = fmaf(-w.Xs[jc * LDN + 64 * k + l], bc, rv[k]);
+        for (int k = 0; k < R; ++k) racc[k] = fma(-(double)w.Xs[jc * LDN + 64 * k + l], bc, racc[k]);
     }
+#pragma unroll
+    for (int k = 0; k < R; ++k) rv[k] = (float)racc[k];
 #pragma unroll
     for (int k = 0; k < R; ++k)
         if ((zbits >> k) & 1u) rv[k] = 0.f;
