@@ -824,10 +824,17 @@ LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, f
     constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id(), p = w.p;
     const float lam = w.lam;
+    float fprev = FINF;
     for (int it = 0;; ++it) {
         if (!vertex_eval<R, XG>(w, rv, zbits, s, f)) return ST_NOTCERT;
         if (certificate<R, XG>(w, rv, zbits, s, u, c, unique)) return unique ? ST_CERTIFIED : ST_NONUNIQUE;
         if (it >= maxp) return ST_MAXITER;
+        // After a step that did not lower f measurably (a degenerate or
+        // nearly degenerate vertex), the released constraint is the violated
+        // one of lowest index (Bland's rule: rows of Z by row index, then
+        // axes), so the steps cannot cycle; otherwise the steepest.
+        const bool bland = !(f < fprev - 1e-7f * fabsf(fprev));
+        fprev = f;
         const int zl = (l < s) ? w.zs[l] : 0;
         const int jl = (l < s) ? w.ss[l] : 0;
         uint32_t smask = 0;
@@ -836,11 +843,28 @@ LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, f
         const float colabs = (l < p) ? w.vca[l] : 0.f;
         float vr = (l < s && 1.f - fabsf(u) < -TOL_U) ? 1.f - fabsf(u) : FINF;
         float vcl = (offS && fabsf(c) > lam * (1.f + TOL_C) + TOL_CA * colabs) ? lam - fabsf(c) : FINF;
-        float m = wmin(fminf(vr, vcl));
-        if (m == FINF) return ST_NOTCERT;
-        uint64_t rbal = ballot(vr == m);
-        const bool type1 = rbal != 0;
-        const int sel = type1 ? first_lane(rbal) : first_lane(ballot(vcl == m));
+        float m;
+        bool type1;
+        int sel;
+        if (!bland) {
+            m = wmin(fminf(vr, vcl));
+            if (m == FINF) return ST_NOTCERT;
+            const uint64_t rbal = ballot(vr == m);
+            type1 = rbal != 0;
+            sel = type1 ? first_lane(rbal) : first_lane(ballot(vcl == m));
+        } else {
+            const int kmin = wmin_i((vr < FINF) ? zl : INT_MAX);
+            type1 = kmin != INT_MAX;
+            if (type1) {
+                sel = first_lane(ballot(vr < FINF && zl == kmin));
+                m = rdlane(vr, sel);
+            } else {
+                const uint64_t cb = ballot(vcl < FINF);
+                if (!cb) return ST_NOTCERT;
+                sel = first_lane(cb);
+                m = rdlane(vcl, sel);
+            }
+        }
         float rhs = 0.f, dj0 = 0.f, usel = 0.f;
         if (type1) {
             usel = rdlane(u, sel);
