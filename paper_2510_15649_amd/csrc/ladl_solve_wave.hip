@@ -16,7 +16,7 @@
 // Layout in LDS (floats), per wave:
 //   Xs  p columns of LDN = 64R+1 floats; row i of column j at j*LDN + i,
 //       row i owned by lane i%64, register slot i/64 (rows >= n are 0)
-//   ys, rn   y and the row norms ||x_i||_2, LDN each
+//   ys  y, LDN floats (row norms ||x_i||_2 are recomputed where needed)
 //   A   vertex matrix / LU factors, pmax rows of 33
 //   A0  the vertex matrix unfactored (refinement residuals), pmax x (pmax+1)
 //   small vectors of 32 (b, best b, column |x| sums, direction, scratch)
@@ -34,21 +34,21 @@ __device__ __forceinline__ float unif(float v) { return bitsf(__builtin_amdgcn_r
 
 __host__ __device__ constexpr int wave_ldn(int R) { return 64 * R + 1; }
 
-// LDS floats per wave: gd, [Xs, ys, rn when resident], best residuals,
+// LDS floats per wave: gd, [Xs, ys when resident], best residuals,
 // A (pmax rows), A0, 6 vectors, sa/sw, zs/ss/piv
 __host__ __device__ constexpr size_t wave_lds_floats(int R, int pmax, bool xg)
 {
-    return 64 + (xg ? 0 : (size_t)(pmax + 2) * wave_ldn(R)) + 64 * (size_t)R + (size_t)pmax * ALD +
+    return 64 + (xg ? 0 : (size_t)(pmax + 1) * wave_ldn(R)) + 64 * (size_t)R + (size_t)pmax * ALD +
            (size_t)pmax * (pmax + 1) + 6 * 32 + 128 + 3 * 32;
 }
-// global workspace floats per wave when X is not LDS-resident: Xs, ys, rn
-__host__ __device__ constexpr size_t wave_ws_floats(int R, int pmax) { return (size_t)(pmax + 2) * wave_ldn(R); }
+// global workspace floats per wave when X is not LDS-resident: Xs, ys
+__host__ __device__ constexpr size_t wave_ws_floats(int R, int pmax) { return (size_t)(pmax + 1) * wave_ldn(R); }
 
 template <int R, bool XG>
 struct Wave {
     static constexpr int LDN = wave_ldn(R);
-    // Xs, ys, rn: LDS (XG false) or this wave's slice of a global workspace
-    float *Xs, *ys, *rn, *rbuf, *A, *A0, *vb, *vbb, *vca, *vd, *vg, *vt, *sa, *sw;
+    // Xs, ys: LDS (XG false) or this wave's slice of a global workspace
+    float *Xs, *ys, *rbuf, *A, *A0, *vb, *vbb, *vca, *vd, *vg, *vt, *sa, *sw;
     double *gd;
     int *zs, *ss, *piv;
     int n, p, nslot, a0ld;
@@ -69,8 +69,6 @@ LADL_INL void carve(Wave<R, XG> &w, float *smem, int pmax, float *ws)
     w.Xs = big;
     big += (size_t)pmax * LDN;
     w.ys = big;
-    big += LDN;
-    w.rn = big;
     big += LDN;
     if (!XG) q = big;
     w.rbuf = q;
@@ -128,10 +126,7 @@ LADL_INL bool load_problem(Wave<R, XG> &w, const float *__restrict__ X, const fl
     const int l = lane_id(), n = w.n, p = w.p, top = 64 * R;
     for (int j = 0; j < p; ++j)
         for (int i = n + l; i < top; i += 64) w.Xs[j * LDN + i] = 0.f;
-    for (int i = n + l; i < top; i += 64) {
-        w.ys[i] = 0.f;
-        w.rn[i] = 0.f;
-    }
+    for (int i = n + l; i < top; i += 64) w.ys[i] = 0.f;
     bool finite = true;
     const int np = n * p;
     const float invp = 1.0f / (float)p;
@@ -149,15 +144,6 @@ LADL_INL bool load_problem(Wave<R, XG> &w, const float *__restrict__ X, const fl
         float v = y[i];
         w.ys[i] = v;
         finite = finite && __builtin_isfinite(v);
-    }
-    ws_sync<XG>();
-    for (int i = l; i < n; i += 64) {
-        float s2 = 0.f;
-        for (int j = 0; j < p; ++j) {
-            float x = w.Xs[j * LDN + i];
-            s2 = fmaf(x, x, s2);
-        }
-        w.rn[i] = sqrtf(s2);
     }
     ws_sync<XG>();
     for (int j = 0; j < p; ++j) {
@@ -527,6 +513,25 @@ LADL_INL float ccd(Wave<R, XG> &w, float (&r)[R], float &bv, int frozen, float f
 // H7: vertices, LU in LDS, certificate, finisher
 // --------------------------------------------------------------------------
 
+// ||x_i||_2 of the lane's rows (0 for padding rows)
+template <int R, bool XG>
+LADL_INL void row_norms(const Wave<R, XG> &w, float (&nr)[R])
+{
+    constexpr int LDN = Wave<R, XG>::LDN;
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 0; k < R; ++k) nr[k] = 0.f;
+    for (int j = 0; j < w.p; ++j) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const float x = w.Xs[j * LDN + 64 * k + l];
+            nr[k] = fmaf(x, x, nr[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) nr[k] = sqrtf(nr[k]);
+}
+
 // The vertex nearest to the point (vb, r): of the hyperplanes
 // {x_i.b = y_i} and {b_j = 0}, take p that meet in one point, nearest first
 // (rows |r_i|/||x_i||, axes |b_j|; ties: axes first, then lower row).  A
@@ -540,11 +545,9 @@ LADL_INL int choose_vertex(Wave<R, XG> &w, const float (&r)[R], float bv, uint32
     constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id(), p = w.p;
     float dist[R];
+    row_norms<R, XG>(w, dist);
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        float nr = (k < w.nslot) ? w.rn[64 * k + l] : 0.f;
-        dist[k] = (nr > 0.f) ? fabsf(r[k]) / nr : FINF;
-    }
+    for (int k = 0; k < R; ++k) dist[k] = (dist[k] > 0.f) ? fabsf(r[k]) / dist[k] : FINF;
     const float dv = (l < p) ? fabsf(bv) : FINF;
     float *Q = w.A;
     zbits = 0;
@@ -801,12 +804,11 @@ LADL_INL bool certificate(Wave<R, XG> &w, const float (&rv)[R], uint32_t zbits, 
     const bool viol = offS && (cabs > w.lam * (1.f + TOL_C) + TOL_CA * colabs);
     const bool cert = (umax <= 1.f + TOL_U) && (ballot(viol) == 0);
     const float mc = wmin(offS ? (w.lam - cabs) / (w.lam + colabs) : FINF);
-    float mr = FINF;
+    float mr = FINF, nr[R];
+    row_norms<R, XG>(w, nr);
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        float nr = (k < w.nslot) ? w.rn[64 * k + l] : 0.f;
-        if (!((zbits >> k) & 1u) && nr > 0.f) mr = fminf(mr, fabsf(rv[k]) / nr);
-    }
+    for (int k = 0; k < R; ++k)
+        if (!((zbits >> k) & 1u) && nr[k] > 0.f) mr = fminf(mr, fabsf(rv[k]) / nr[k]);
     mr = wmin(mr);
     unique = cert && (1.f - umax > MARGIN_U) && (mc > MARGIN_C) && (mr > MARGIN_R * (1.f + w.ynorm1 / w.n));
     return cert;
