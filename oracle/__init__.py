@@ -25,7 +25,7 @@ STAGE_CCD, STAGE_TERNARY, STAGE_FINISHER, STAGE_NONE = 0, 1, 100, -1
 class Opts(C.Structure):
     _fields_ = [("tol_f", C.c_double), ("tol_s", C.c_double), ("lambda_min", C.c_double),
                 ("max_sweeps", C.c_int), ("max_ternary", C.c_int), ("max_rounds", C.c_int),
-                ("max_pivots", C.c_int), ("use_finisher", C.c_int)]
+                ("max_pivots", C.c_int), ("use_finisher", C.c_int), ("chop_range", C.c_double)]
 
 
 class Prob(C.Structure):

@@ -36,6 +36,7 @@ void orc_default_opts(orc_opts *o)
     o->max_rounds = -1;
     o->max_pivots = 0; /* 0: 4*(n+p) */
     o->use_finisher = 1;
+    o->chop_range = 1.0 / 32.0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -599,8 +600,10 @@ int orc_certify(const orc_prob *P, double lambda, double *b, double *u, orc_info
 /*                                                                           */
 /* F(s): from the best point found so far, set b_k := s and run CCD with     */
 /* axis k frozen (the restricted sub-search); F(s) is the objective reached. */
-/* The initial range c +- max(1,|c|) around the current b_k is extended by   */
-/* doubling while an end point is lower than the centre, clamped to           */
+/* The initial range c +- h, h = chop_range * max(1,|c|), around the current */
+/* b_k (the paper leaves the initial range to the user and extends it until  */
+/* it holds the minimum, Section 3.6) is doubled outward while an end point */
+/* is lower than the centre, clamped to                                       */
 /* |b_k| <= ||y||_1 / lambda (any minimiser has lambda ||b||_1 <= f(0)).      */
 /* The range is then cut in thirds; the best probe is kept.                  */
 /* ------------------------------------------------------------------------ */
@@ -646,7 +649,7 @@ static void ternary(otern *T)
         B = y1 / T->lam;
     }
     double c = T->b[T->k];
-    double h = fmax(1.0, fabs(c));
+    double h = T->o->chop_range * fmax(1.0, fabs(c));
     double lo = fmax(c - h, -B), hi = fmin(c + h, B);
     double Fc = T->f;
     double Flo = probe(T, lo), Fhi = probe(T, hi);

@@ -45,6 +45,7 @@ typedef struct {
     int max_rounds;    /* ternary rounds over successive axes; <0 means p          */
     int max_pivots;    /* edge-descent finisher pivot cap                          */
     int use_finisher;  /* 1: run the finisher when the paper's stages fail         */
+    double chop_range; /* initial chop half-width, a fraction of max(1, |b_k|)     */
 } orc_opts;
 
 /* stage codes reported by orc_solve */
