@@ -35,7 +35,8 @@ EXPORTED = ["ladl_create", "ladl_destroy", "ladl_default_options", "ladl_plan_cr
 class Options(C.Structure):
     _fields_ = [("tol_f", C.c_float), ("tol_s", C.c_float), ("lambda_min", C.c_float),
                 ("max_sweeps", C.c_int32), ("max_ternary", C.c_int32), ("max_rounds", C.c_int32),
-                ("max_pivots", C.c_int32), ("flags", C.c_int32), ("schedule", C.c_int32)]
+                ("max_pivots", C.c_int32), ("flags", C.c_int32), ("schedule", C.c_int32),
+                ("chop_range", C.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

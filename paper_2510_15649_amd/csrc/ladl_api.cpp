@@ -127,6 +127,7 @@ void ladl_default_options(ladl_options *o)
     o->max_pivots = 0;
     o->flags = 0;
     o->schedule = -1;
+    o->chop_range = 0.03125f;
 }
 
 int ladl_create(ladl_handle_t *handle)
@@ -172,6 +173,8 @@ static int check_options(const ladl_options *o)
     if (o->max_pivots < 0 || o->max_pivots > 100000) return fail(LADL_EINVAL, "max_pivots out of [0, 100000]");
     if (o->flags & ~KNOWN_FLAGS) return fail(LADL_EINVAL, "unknown flag bits 0x%x", o->flags & ~KNOWN_FLAGS);
     if (o->schedule < -1 || o->schedule > 0) return fail(LADL_EINVAL, "unknown schedule %d", o->schedule);
+    if (!(o->chop_range > 0.f) || !std::isfinite(o->chop_range))
+        return fail(LADL_EINVAL, "chop_range must be finite and > 0");
     return LADL_OK;
 }
 
@@ -310,7 +313,7 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         for (int s : ids) b.pmax = std::max(b.pmax, (int)pl->p[pl->problem[s]]);
         b.count = (int)ids.size();
         order.insert(order.end(), ids.begin(), ids.end());
-        const bool xg = R >= 32 || wave_lds_bytes(R, b.pmax, false) > LDS_RESIDENT_MAX;
+        const bool xg = o.schedule == 0 || R >= 32 || wave_lds_bytes(R, b.pmax, false) > LDS_RESIDENT_MAX;
         size_t lds = wave_lds_bytes(R, b.pmax, xg);
         if (lds > h->lds_max)
             return bad(LADL_EUNSUPPORTED, "bucket R=%d p=%d needs %zu bytes of LDS (device limit %zu)", R, b.pmax,
@@ -388,6 +391,7 @@ static DevOpt dev_opt(const ladl_options &o)
     d.max_rounds = o.max_rounds;
     d.max_pivots = o.max_pivots;
     d.flags = o.flags;
+    d.chop_range = o.chop_range;
     return d;
 }
 
@@ -662,6 +666,7 @@ int ladl_autotune(ladl_plan_t pl, const float *X, const float *y, const float *l
 {
     int rc = check_solve_ptrs(pl, X, y, lam, b, obj, active, zr, st);
     if (rc) return rc;
+    if (pl->opt.schedule == 0) return LADL_OK; // the caller fixed the schedule
     hipStream_t s = (hipStream_t)stream;
     const std::string dev = device_name(pl->h->device);
     hipEvent_t e0 = nullptr, e1 = nullptr;

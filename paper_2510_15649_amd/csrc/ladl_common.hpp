@@ -43,8 +43,10 @@ constexpr float PERTURB_REL = 1.52587890625e-05f; // 2^-16
 // H6: ternary chop along axis kax (Sections 3.5-3.6), as a state machine fed
 // with one probe value F(s) at a time so that the solve has a single CCD
 // call site.  F(s) = f after CCD with b_kax := s and axis kax frozen,
-// started from the best point found so far.  The range c +- max(1,|c|) is
-// extended by doubling while an end is lower than the centre (clamped to
+// started from the best point found so far.  The range c +- h,
+// h = chop_range * max(1,|c|) (the paper leaves the initial range open and
+// extends it until it holds the minimum), is doubled outward while an end
+// is lower than the centre (clamped to
 // |b_kax| <= ||y||_1 / lambda, which bounds every minimiser), then cut in
 // thirds (or golden sections) keeping the better side.
 // --------------------------------------------------------------------------
@@ -54,11 +56,11 @@ struct Chop {
     bool have1, have2;
 };
 
-LADL_INL void chop_init(Chop &q, float c, float f, float B)
+LADL_INL void chop_init(Chop &q, float c, float f, float B, float range)
 {
     q.B = B;
     q.c = c;
-    q.h = fmaxf(1.f, fabsf(c));
+    q.h = range * fmaxf(1.f, fabsf(c));
     q.lo = fmaxf(c - q.h, -B);
     q.hi = fminf(c + q.h, B);
     q.Fc = f;

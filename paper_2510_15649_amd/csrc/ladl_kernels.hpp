@@ -12,6 +12,7 @@ constexpr int ZPAD = 32;     // zero_rows entries per output
 struct DevOpt {
     float tol_f, tol_s, lambda_min;
     int max_sweeps, max_ternary, max_rounds, max_pivots, flags;
+    float chop_range;
 };
 
 // One launch of the forward solve over a list of solves (one bucket).

@@ -652,7 +652,7 @@ __device__ void pt_solve_item(PT &t, const SolveArgs &a, int s)
                     for (int j = 0; j < p; ++j) t.bb[j] = t.b[j];
                     for (int i = 0; i < n; ++i) t.rb[i] = t.r[i];
                     fbest = f;
-                    chop_init(q, t.bb[kax], f, B);
+                    chop_init(q, t.bb[kax], f, B, t.opt.chop_range);
                     more = chop_next(q, 0.f, sprobe, t.opt);
                 } else {
                     t.c_probes++;

@@ -1080,7 +1080,7 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
 #pragma unroll
                     for (int kk = 0; kk < R; ++kk) w.rbuf[64 * kk + l] = r[kk];
                     fbest = f;
-                    chop_init(q, rdlane(bbv, kax), f, B);
+                    chop_init(q, rdlane(bbv, kax), f, B, w.opt.chop_range);
                     more = chop_next(q, 0.f, sprobe, w.opt);
                 } else {
                     w.c_probes++;

@@ -29,6 +29,7 @@ def test_host_only_entry_points():
     o = L.default_options()
     assert o.max_sweeps == 64 and o.max_rounds == 1 and o.schedule == -1
     assert abs(o.tol_s - 2 ** -20) < 1e-12
+    assert o.chop_range == 2 ** -5
     assert lib.ladl_error_string(L.EINVAL).startswith(b"LADL_EINVAL")
     assert lib.ladl_error_string(L.OK) == b"LADL_OK"
     # NULL arguments are rejected before any device work
