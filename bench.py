@@ -332,7 +332,10 @@ def main():
         import oracle as O
         threads = min(os.cpu_count() or 1, 16)
         rng = np.random.default_rng(99)
-        opts = dict(max_rounds=args.max_rounds, tol_f=1e-6, tol_s=2.0 ** -20, max_sweeps=64, max_ternary=48)
+        d_opt = L.default_options()
+        opts = dict(max_rounds=args.max_rounds, tol_f=float(d_opt.tol_f), tol_s=float(d_opt.tol_s),
+                    max_sweeps=int(d_opt.max_sweeps), max_ternary=int(d_opt.max_ternary),
+                    chop_range=float(d_opt.chop_range))
         k = min(w.num_solves, 64)
         while True:
             solves = np.sort(rng.choice(w.num_solves, size=k, replace=False))

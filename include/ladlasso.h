@@ -79,7 +79,9 @@ typedef struct {
     float lambda_min;    /* effective lambda = max(lambda, lambda_min); the
                             paper's tie-breaking minimum (Section 3.6)
                                                               (default 0)     */
-    int32_t max_sweeps;  /* sweeps per CCD run                (default 64)    */
+    int32_t max_sweeps;  /* sweeps per CCD run (a cap on the rare slowly
+                            zig-zagging probes; the certificate and the
+                            finisher do not depend on it)     (default 8)     */
     int32_t max_ternary; /* chop iterations per round         (default 48)    */
     int32_t max_rounds;  /* chop rounds, each on the next axis: 0 none,
                             -1 one per axis                   (default 1)     */

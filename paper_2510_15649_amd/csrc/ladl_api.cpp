@@ -121,7 +121,7 @@ void ladl_default_options(ladl_options *o)
     o->tol_f = 1e-6f;
     o->tol_s = 9.5367431640625e-07f; // 2^-20
     o->lambda_min = 0.f;
-    o->max_sweeps = 64;
+    o->max_sweeps = 8;
     o->max_ternary = 48;
     o->max_rounds = 1;
     o->max_pivots = 0;

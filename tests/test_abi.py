@@ -27,7 +27,7 @@ def test_header_symbols_exported():
 def test_host_only_entry_points():
     lib = L.lib()
     o = L.default_options()
-    assert o.max_sweeps == 64 and o.max_rounds == 1 and o.schedule == -1
+    assert o.max_sweeps == 8 and o.max_rounds == 1 and o.schedule == -1
     assert abs(o.tol_s - 2 ** -20) < 1e-12
     assert o.chop_range == 2 ** -5
     assert lib.ladl_error_string(L.EINVAL).startswith(b"LADL_EINVAL")
