@@ -1430,7 +1430,9 @@ __global__ __launch_bounds__(64) void k_bw_scatter(BackwardArgs a)
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s)
 {
     const int64_t f4s = (a.x_len + a.y_len) / 4 + 2;
-    const int fill_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((f4s + 63) / 64, 2048));
+    // two fill waves per CU: measured fastest (more fill waves crowd out the
+    // vertex waves they are meant to overlap: 5.0 TB/s at 512, 3.7 at 2048)
+    const int fill_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((f4s + 63) / 64, 512));
     hipLaunchKernelGGL(k_bw_vertex, dim3(fill_blocks + a.num_solves), dim3(64), 0, s, a, fill_blocks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
