@@ -71,7 +71,8 @@ def test_c2_subset(torch, kernel):
 
 
 @pytest.mark.parametrize("opts", [dict(max_rounds=0), dict(max_rounds=1, flags=L.FLAG_GOLDEN),
-                                  dict(max_rounds=2, tol_s=1e-3)])
+                                  dict(max_rounds=2, tol_s=1e-3), dict(chop_range=1.0, max_sweeps=64),
+                                  dict(chop_range=1e-3, max_sweeps=1), dict(max_rounds=-1, schedule=0)])
 def test_schedules(torch, opts):
     w = W.config1(num_problems=16)
     plan, g = gpu_solve(torch, w, **opts)
@@ -158,6 +159,9 @@ def test_validation_errors(torch):
     assert e.value.code == L.EINVAL
     with pytest.raises(L.LadlError) as e:
         L.Plan(ro, 3, x_len=60, y_len=20, max_sweeps=0)
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LadlError) as e:
+        L.Plan(ro, 3, x_len=60, y_len=20, chop_range=0.0)
     assert e.value.code == L.EINVAL
 
 
