@@ -88,9 +88,14 @@ typedef struct {
     int32_t max_pivots;  /* finisher pivots; <= 0 means 4p + 32 (default 0)   */
     int32_t flags;       /* LADL_FLAG_*                       (default 0)     */
     int32_t schedule;    /* -1: per bucket, X in LDS when it fits 40 KB per
-                            wave, else in an HBM workspace (ladl_autotune
-                            may change the choice); 0: the HBM workspace
-                            for every bucket                  (default -1)    */
+                            wave, else in an HBM workspace, and for
+                            n <= 256 with more than two grids' worth of
+                            solves the HBM workspace with the kernel
+                            variant built for 5 waves per SIMD
+                            (ladl_autotune may change the choice);
+                            0: the HBM workspace for every bucket;
+                            1: as 0, with the 5-wave variant wherever
+                            n <= 256                          (default -1)    */
     float chop_range;    /* initial half-width of the chop's range around
                             b_k, as a fraction of max(1, |b_k|); the range
                             is doubled while an end is lower than the
@@ -212,11 +217,13 @@ int ladl_graph_destroy(ladl_graph_t graph);
 /*
  * Time each candidate schedule on this plan's own data (runs the solve
  * several times on `stream`, synchronously) and keep the fastest per
- * bucket in the plan: X resident in LDS or in the HBM workspace, for the
- * buckets where both exist.  The choice is cached in the file named by the
- * environment variable LADL_TUNE_CACHE (if set), keyed by device, rows per
- * lane and p_max.  Optional: plans start with a static choice; a plan
- * created with options.schedule = 0 is left as it is.
+ * bucket in the plan: X resident in LDS, X in the HBM workspace, and (for
+ * n <= 256) X in the HBM workspace with the 5-waves-per-SIMD kernel
+ * variant, for the buckets where more than one exists.  The choice is
+ * cached in the file named by the environment variable LADL_TUNE_CACHE (if
+ * set), keyed by device, rows per lane and p_max.  Optional: plans start
+ * with a static choice; a plan created with options.schedule = 0 or 1 is
+ * left as it is.
  */
 int ladl_autotune(ladl_plan_t plan, const float *X, const float *y, const float *lambda, float *b,
                   float *obj, uint32_t *active, int32_t *zero_rows, int32_t *status, void *stream);

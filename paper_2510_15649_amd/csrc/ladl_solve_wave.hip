@@ -1191,18 +1191,19 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
     }
 }
 
-// Optional occupancy target (waves per SIMD) imposed on the register
-// allocation; 0 (default) leaves it to the compiler.  Measured on the
-// ragged workloads: an explicit target, even one the allocation already
-// meets, made the n <= 1024 bucket slower (2.3x in the vertex phase), so
-// none is set.
-#ifndef LADL_WAVES_PER_EU
-#define LADL_WAVES_PER_EU 0
-#endif
-__host__ __device__ constexpr int waves_per_eu(int) { return LADL_WAVES_PER_EU > 0 ? LADL_WAVES_PER_EU : 1; }
+// Register budget.  Left to the compiler, the R <= 4 kernels take 124-144
+// VGPRs (3-4 waves per SIMD), most of it live only in the vertex, chop and
+// finisher code.  The DENSE variant asks for 5 waves per SIMD (96 VGPRs):
+// the compiler then spills a few values of the per-probe chop logic, and the
+// coordinate-update loop stays spill-free.  It only pays where the X
+// workspace is in HBM (LDS would cap the waves first) and the bucket has
+// solves enough to fill the extra waves; for R >= 8 the spills reach the
+// update loop (the n <= 1024 bucket ran 1.5-2x slower), so it is not built.
+constexpr int DENSE_WAVES_PER_SIMD = 5;
+__host__ __device__ constexpr int waves_per_eu(bool dense) { return dense ? DENSE_WAVES_PER_SIMD : 1; }
 
-template <int R, bool XG>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
+template <int R, bool XG, bool DENSE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_eu(DENSE))))
 void k_wave(SolveArgs a)
 {
     extern __shared__ float smem[];
@@ -1234,72 +1235,94 @@ hipError_t launch_reset(int32_t *counters, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int R, bool XG>
+template <int R, bool XG, bool DENSE>
 static hipError_t launch_wave_t(const SolveArgs &a, int grid, hipStream_t s)
 {
     size_t lds = wave_lds_bytes(R, a.pmax, XG);
     static bool attr = false;
     if (!attr) {
         // allow dynamic LDS beyond the default limit; harmless if refused
-        (void)hipFuncSetAttribute((const void *)k_wave<R, XG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void *)k_wave<R, XG, DENSE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((k_wave<R, XG>), dim3(grid), dim3(64), lds, s, a);
+    hipLaunchKernelGGL((k_wave<R, XG, DENSE>), dim3(grid), dim3(64), lds, s, a);
     return hipGetLastError();
 }
 
-template <int R, bool XG>
+template <int R, bool XG, bool DENSE>
 static int max_blocks_t(int pmax)
 {
     int nb = 0;
     size_t lds = wave_lds_bytes(R, pmax, XG);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_wave<R, XG>, 64, lds) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_wave<R, XG, DENSE>, 64, lds) != hipSuccess) return 0;
     return nb;
 }
 
-hipError_t launch_wave(int R, bool xg, const SolveArgs &a, int grid, hipStream_t s)
+bool wave_has_dense(int R) { return R == 1 || R == 2 || R == 4; }
+
+// the variants that exist: R in {1,2,4,8,16} with X in LDS or HBM, R = 32
+// with X in HBM, and the dense register budget for R <= 4 with X in HBM
+hipError_t launch_wave(int R, bool xg, bool dense, const SolveArgs &a, int grid, hipStream_t s)
 {
+    if (dense) {
+        if (!xg) return hipErrorInvalidValue;
+        switch (R) {
+        case 1: return launch_wave_t<1, true, true>(a, grid, s);
+        case 2: return launch_wave_t<2, true, true>(a, grid, s);
+        case 4: return launch_wave_t<4, true, true>(a, grid, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (xg) {
         switch (R) {
-        case 1: return launch_wave_t<1, true>(a, grid, s);
-        case 2: return launch_wave_t<2, true>(a, grid, s);
-        case 4: return launch_wave_t<4, true>(a, grid, s);
-        case 8: return launch_wave_t<8, true>(a, grid, s);
-        case 16: return launch_wave_t<16, true>(a, grid, s);
-        case 32: return launch_wave_t<32, true>(a, grid, s);
+        case 1: return launch_wave_t<1, true, false>(a, grid, s);
+        case 2: return launch_wave_t<2, true, false>(a, grid, s);
+        case 4: return launch_wave_t<4, true, false>(a, grid, s);
+        case 8: return launch_wave_t<8, true, false>(a, grid, s);
+        case 16: return launch_wave_t<16, true, false>(a, grid, s);
+        case 32: return launch_wave_t<32, true, false>(a, grid, s);
         default: return hipErrorInvalidValue;
         }
     }
     switch (R) {
-    case 1: return launch_wave_t<1, false>(a, grid, s);
-    case 2: return launch_wave_t<2, false>(a, grid, s);
-    case 4: return launch_wave_t<4, false>(a, grid, s);
-    case 8: return launch_wave_t<8, false>(a, grid, s);
-    case 16: return launch_wave_t<16, false>(a, grid, s);
+    case 1: return launch_wave_t<1, false, false>(a, grid, s);
+    case 2: return launch_wave_t<2, false, false>(a, grid, s);
+    case 4: return launch_wave_t<4, false, false>(a, grid, s);
+    case 8: return launch_wave_t<8, false, false>(a, grid, s);
+    case 16: return launch_wave_t<16, false, false>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-int wave_max_blocks_per_cu(int R, int pmax, bool xg)
+int wave_max_blocks_per_cu(int R, int pmax, bool xg, bool dense)
 {
+    if (dense) {
+        if (!xg) return 0;
+        switch (R) {
+        case 1: return max_blocks_t<1, true, true>(pmax);
+        case 2: return max_blocks_t<2, true, true>(pmax);
+        case 4: return max_blocks_t<4, true, true>(pmax);
+        default: return 0;
+        }
+    }
     if (xg) {
         switch (R) {
-        case 1: return max_blocks_t<1, true>(pmax);
-        case 2: return max_blocks_t<2, true>(pmax);
-        case 4: return max_blocks_t<4, true>(pmax);
-        case 8: return max_blocks_t<8, true>(pmax);
-        case 16: return max_blocks_t<16, true>(pmax);
-        case 32: return max_blocks_t<32, true>(pmax);
+        case 1: return max_blocks_t<1, true, false>(pmax);
+        case 2: return max_blocks_t<2, true, false>(pmax);
+        case 4: return max_blocks_t<4, true, false>(pmax);
+        case 8: return max_blocks_t<8, true, false>(pmax);
+        case 16: return max_blocks_t<16, true, false>(pmax);
+        case 32: return max_blocks_t<32, true, false>(pmax);
         default: return 0;
         }
     }
     switch (R) {
-    case 1: return max_blocks_t<1, false>(pmax);
-    case 2: return max_blocks_t<2, false>(pmax);
-    case 4: return max_blocks_t<4, false>(pmax);
-    case 8: return max_blocks_t<8, false>(pmax);
-    case 16: return max_blocks_t<16, false>(pmax);
+    case 1: return max_blocks_t<1, false, false>(pmax);
+    case 2: return max_blocks_t<2, false, false>(pmax);
+    case 4: return max_blocks_t<4, false, false>(pmax);
+    case 8: return max_blocks_t<8, false, false>(pmax);
+    case 16: return max_blocks_t<16, false, false>(pmax);
     default: return 0;
     }
 }

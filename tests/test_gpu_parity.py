@@ -72,10 +72,22 @@ def test_c2_subset(torch, kernel):
 
 @pytest.mark.parametrize("opts", [dict(max_rounds=0), dict(max_rounds=1, flags=L.FLAG_GOLDEN),
                                   dict(max_rounds=2, tol_s=1e-3), dict(chop_range=1.0, max_sweeps=64),
-                                  dict(chop_range=1e-3, max_sweeps=1), dict(max_rounds=-1, schedule=0)])
+                                  dict(chop_range=1e-3, max_sweeps=1), dict(max_rounds=-1, schedule=0),
+                                  dict(schedule=1)])
 def test_schedules(torch, opts):
     w = W.config1(num_problems=16)
     plan, g = gpu_solve(torch, w, **opts)
+    assert_parity(w, g, oracle_ref(w))
+
+
+def test_dense_variant_ragged(torch):
+    """Ragged row subsets with every bucket in the HBM workspace and the
+    5-waves-per-SIMD kernel variant for n <= 256."""
+    w = W.config2(num_subsets=160)
+    plan, g = gpu_solve(torch, w, schedule=1)
+    desc = plan.describe()
+    print(desc, flush=True)
+    assert "(dense)" in desc
     assert_parity(w, g, oracle_ref(w))
 
 
@@ -163,6 +175,9 @@ def test_validation_errors(torch):
     with pytest.raises(L.LadlError) as e:
         L.Plan(ro, 3, x_len=60, y_len=20, chop_range=0.0)
     assert e.value.code == L.EINVAL
+    with pytest.raises(L.LadlError) as e:
+        L.Plan(ro, 3, x_len=60, y_len=20, schedule=2)
+    assert e.value.code == L.EINVAL
 
 
 def test_c1_full_size_sampled(torch):
@@ -171,6 +186,7 @@ def test_c1_full_size_sampled(torch):
     of 512 solves."""
     w = W.config1()
     plan, g = gpu_solve(torch, w)
+    print(plan.describe(), flush=True)
     rng = np.random.default_rng(11)
     sample = np.sort(rng.choice(w.num_solves, size=512, replace=False))
     fails, st = compare(w, g, oracle_ref(w, solves=sample), solves=sample)
