@@ -62,6 +62,7 @@ struct Bucket {
     int grid = 0;
     bool xg = false;           // X in the global workspace instead of LDS
     bool dense = false;        // the kernel variant built for 5 waves per SIMD
+    int nlds = 0;              // with the workspace: columns of X kept in LDS
     int per_cu = 0;
     int64_t ws_off = 0;        // this bucket's slice of the workspace
 };
@@ -74,6 +75,7 @@ struct ladl_plan_s {
     int64_t b_len = 0, x_len = 0, y_len = 0;
     ladl_options opt{};
     std::vector<Bucket> buckets;
+    bool multi_bucket = false;   // buckets run side by side and share the CUs
     int64_t *d_row_off = nullptr, *d_x_off = nullptr, *d_b_off = nullptr;
     int32_t *d_p = nullptr, *d_problem = nullptr, *d_order = nullptr, *d_counters = nullptr;
     int32_t *d_order_plain = nullptr, *d_counter_plain = nullptr;
@@ -298,6 +300,14 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
     };
     // buckets by rows per lane; decreasing cost inside a bucket
     std::vector<int> Rs = {32, 16, 8, 4, 2, 1};
+    {
+        uint32_t seen = 0;
+        for (int s = 0; s < S; ++s) {
+            const int k = pl->problem[s];
+            seen |= (uint32_t)rows_per_lane((int)(pl->row_off[k + 1] - pl->row_off[k]));
+        }
+        pl->multi_bucket = __builtin_popcount(seen) > 1;
+    }
     std::vector<int32_t> order;
     order.reserve(S);
     for (int R : Rs) {
@@ -315,8 +325,8 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         for (int s : ids) b.pmax = std::max(b.pmax, (int)pl->p[pl->problem[s]]);
         b.count = (int)ids.size();
         order.insert(order.end(), ids.begin(), ids.end());
-        const bool xg = o.schedule >= 0 || R >= 32 || wave_lds_bytes(R, b.pmax, false) > LDS_RESIDENT_MAX;
-        size_t lds = wave_lds_bytes(R, b.pmax, xg);
+        const bool xg = o.schedule >= 0 || R >= 32 || wave_lds_bytes(R, b.pmax, false, 0) > LDS_RESIDENT_MAX;
+        size_t lds = wave_lds_bytes(R, b.pmax, xg, 0);
         if (lds > h->lds_max)
             return bad(LADL_EUNSUPPORTED, "bucket R=%d p=%d needs %zu bytes of LDS (device limit %zu)", R, b.pmax,
                        lds, h->lds_max);
@@ -448,7 +458,7 @@ static int layout_workspace(ladl_plan_t pl)
     int64_t tot = 0;
     for (Bucket &b : pl->buckets) {
         b.ws_off = tot;
-        if (b.xg) tot += (int64_t)b.grid * (int64_t)wave_ws_floats_host(b.R, b.pmax);
+        if (b.xg) tot += (int64_t)b.grid * (int64_t)wave_ws_floats_host(b.R, b.pmax, b.nlds);
     }
     if (tot > pl->wws_floats || (tot > 0 && !pl->d_wws)) {
         (void)hipFree(pl->d_wws);
@@ -464,7 +474,19 @@ static void set_schedule(ladl_plan_t pl, Bucket &b, bool xg, bool dense)
 {
     b.xg = xg || dense;
     b.dense = dense && wave_has_dense(b.R);
-    b.per_cu = std::max(1, wave_max_blocks_per_cu(b.R, b.pmax, b.xg, b.dense));
+    b.nlds = b.xg ? 0 : b.pmax;
+    b.per_cu = std::max(1, wave_max_blocks_per_cu(b.R, b.pmax, b.xg, b.dense, b.nlds));
+    // With the workspace, keep in LDS as many leading columns of X as the
+    // LDS left over at this occupancy holds.  Where buckets run side by side
+    // that LDS is what lets the other buckets' waves share a CU, so there
+    // only the n > 1024 bucket takes columns (measured on the ragged
+    // workloads: the n <= 2048 bucket 1.5x faster with them; the 4096 row
+    // subsets of the correlated dataset 8% slower when every bucket took
+    // them).
+    const bool take = !pl->multi_bucket || b.R >= 32;
+    while (take && b.xg && b.nlds < b.pmax && wave_lds_bytes(b.R, b.pmax, true, b.nlds + 1) <= pl->h->lds_max &&
+           wave_max_blocks_per_cu(b.R, b.pmax, true, b.dense, b.nlds + 1) >= b.per_cu)
+        ++b.nlds;
     b.grid = (int)std::min<int64_t>(b.count, (int64_t)b.per_cu * pl->h->num_cu);
 }
 
@@ -476,9 +498,10 @@ static hipError_t launch_bucket(ladl_plan_t pl, size_t bi, const SolveArgs &base
     a.num_items = bk.count;
     a.counter = pl->d_counters + bi;
     a.pmax = bk.pmax;
+    a.nlds = bk.nlds;
     if (bk.xg) {
         a.gws = pl->d_wws + bk.ws_off;
-        a.gws_stride = (int64_t)wave_ws_floats_host(bk.R, bk.pmax);
+        a.gws_stride = (int64_t)wave_ws_floats_host(bk.R, bk.pmax, bk.nlds);
     }
     return launch_wave(bk.R, bk.xg, bk.dense, a, bk.grid, s);
 }
@@ -687,7 +710,7 @@ int ladl_autotune(ladl_plan_t pl, const float *X, const float *y, const float *l
     // 2 = the HBM workspace with the dense kernel variant
     for (size_t bi = 0; bi < pl->buckets.size() && rc == LADL_OK; ++bi) {
         Bucket &bk = pl->buckets[bi];
-        const bool can_lds = bk.R < 32 && wave_lds_bytes(bk.R, bk.pmax, false) <= pl->h->lds_max;
+        const bool can_lds = bk.R < 32 && wave_lds_bytes(bk.R, bk.pmax, false, 0) <= pl->h->lds_max;
         const bool can_dense = wave_has_dense(bk.R);
         if (!can_lds && !can_dense) continue; // only the workspace schedule exists
         int cached = cache_lookup(dev, bk.R, bk.pmax);
@@ -736,9 +759,13 @@ int ladl_plan_describe(ladl_plan_t pl, char *buf, int64_t len)
              pl->L, pl->nmax, pl->pmax, (long long)pl->b_len);
     s += line;
     for (const Bucket &b : pl->buckets) {
-        snprintf(line, sizeof line, "bucket R=%d (n<=%d) pmax=%d solves=%d grid=%d (%d/CU) X in %s%s lds=%zuB\n", b.R,
-                 64 * b.R, b.pmax, b.count, b.grid, b.per_cu, b.xg ? "HBM workspace" : "LDS",
-                 b.dense ? " (dense)" : "", wave_lds_bytes(b.R, b.pmax, b.xg));
+        char place[64];
+        if (b.xg)
+            snprintf(place, sizeof place, "HBM workspace, %d columns in LDS%s", b.nlds, b.dense ? " (dense)" : "");
+        else
+            snprintf(place, sizeof place, "LDS");
+        snprintf(line, sizeof line, "bucket R=%d (n<=%d) pmax=%d solves=%d grid=%d (%d/CU) X in %s lds=%zuB\n", b.R,
+                 64 * b.R, b.pmax, b.count, b.grid, b.per_cu, place, wave_lds_bytes(b.R, b.pmax, b.xg, b.nlds));
         s += line;
     }
     std::strncpy(buf, s.c_str(), (size_t)len - 1);

@@ -32,6 +32,7 @@ struct SolveArgs {
     int64_t gws_stride;   // floats per thread
     DevOpt opt;
     int32_t pmax;         // largest p in the bucket (LDS carve-up)
+    int32_t nlds;         // with the workspace: columns of X kept in LDS
 };
 
 struct BackwardArgs {
@@ -73,12 +74,13 @@ struct BruteArgs {
 
 // host-side launchers (defined in ladl_kernels.hip)
 // wave kernel: R = row slots per lane (1..32); xg = X held in a per-wave
-// global workspace instead of LDS (required for R = 32); dense = the
-// variant compiled for 5 waves per SIMD (R <= 4 with xg only)
-size_t wave_lds_bytes(int R, int pmax, bool xg);
-size_t wave_ws_floats_host(int R, int pmax);
+// global workspace instead of LDS (required for R = 32), except its first
+// nlds columns; dense = the variant compiled for 5 waves per SIMD (R <= 4
+// with xg only)
+size_t wave_lds_bytes(int R, int pmax, bool xg, int nlds);
+size_t wave_ws_floats_host(int R, int pmax, int nlds);
 bool wave_has_dense(int R);
-int wave_max_blocks_per_cu(int R, int pmax, bool xg, bool dense);
+int wave_max_blocks_per_cu(int R, int pmax, bool xg, bool dense, int nlds);
 hipError_t launch_reset(int32_t *counters, int n, hipStream_t s);
 hipError_t launch_wave(int R, bool xg, bool dense, const SolveArgs &a, int grid, hipStream_t s);
 hipError_t launch_plain(const SolveArgs &a, int NM, int64_t nthreads, hipStream_t s);

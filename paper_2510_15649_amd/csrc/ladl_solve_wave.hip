@@ -17,6 +17,10 @@
 //   Xs  p columns of LDN = 64R+1 floats; row i of column j at j*LDN + i,
 //       row i owned by lane i%64, register slot i/64 (rows >= n are 0)
 //   ys  y, LDN floats (row norms ||x_i||_2 are recomputed where needed)
+// With the HBM workspace (XG), only the first nlds columns stay in LDS (as
+// many as the LDS left over at the kernel's register-bound occupancy
+// holds); the other columns and y live in the wave's workspace slice, in
+// the same column layout.
 //   A   vertex matrix / LU factors, pmax rows of 33
 //   A0  the vertex matrix unfactored (refinement residuals), pmax x (pmax+1)
 //   small vectors of 32 (b, best b, column |x| sums, direction, scratch)
@@ -34,24 +38,31 @@ __device__ __forceinline__ float unif(float v) { return bitsf(__builtin_amdgcn_r
 
 __host__ __device__ constexpr int wave_ldn(int R) { return 64 * R + 1; }
 
-// LDS floats per wave: gd, [Xs, ys when resident], best residuals,
-// A (pmax rows), A0, 6 vectors, sa/sw, zs/ss/piv
-__host__ __device__ constexpr size_t wave_lds_floats(int R, int pmax, bool xg)
+// LDS floats per wave: gd, [Xs, ys when resident; the first nlds columns
+// of Xs with the workspace], best residuals, A (pmax rows), A0, 6 vectors,
+// sa/sw, zs/ss/piv
+__host__ __device__ constexpr size_t wave_lds_floats(int R, int pmax, bool xg, int nlds)
 {
-    return 64 + (xg ? 0 : (size_t)(pmax + 1) * wave_ldn(R)) + 64 * (size_t)R + (size_t)pmax * ALD +
+    return 64 + (size_t)(xg ? nlds : pmax + 1) * wave_ldn(R) + 64 * (size_t)R + (size_t)pmax * ALD +
            (size_t)pmax * (pmax + 1) + 6 * 32 + 128 + 3 * 32;
 }
-// global workspace floats per wave when X is not LDS-resident: Xs, ys
-__host__ __device__ constexpr size_t wave_ws_floats(int R, int pmax) { return (size_t)(pmax + 1) * wave_ldn(R); }
+// global workspace floats per wave with the workspace: columns nlds .. p-1
+// of Xs, then ys
+__host__ __device__ constexpr size_t wave_ws_floats(int R, int pmax, int nlds)
+{
+    return (size_t)(pmax + 1 - nlds) * wave_ldn(R);
+}
 
 template <int R, bool XG>
 struct Wave {
     static constexpr int LDN = wave_ldn(R);
-    // Xs, ys: LDS (XG false) or this wave's slice of a global workspace
-    float *Xs, *ys, *rbuf, *A, *A0, *vb, *vbb, *vca, *vd, *vg, *vt, *sa, *sw;
+    // Xs: the LDS columns of X (all of them without the workspace); Xg: the
+    // workspace columns (column j >= nlds at (j - nlds) * LDN); ys: y, in
+    // LDS without the workspace, else after the workspace columns
+    float *Xs, *Xg, *ys, *rbuf, *A, *A0, *vb, *vbb, *vca, *vd, *vg, *vt, *sa, *sw;
     double *gd;
     int *zs, *ss, *piv;
-    int n, p, nslot, a0ld;
+    int n, p, nslot, a0ld, nlds;
     float lam, ynorm1;
     float cav; // lane j: sum_i |x_ij|
     DevOpt opt;
@@ -59,18 +70,25 @@ struct Wave {
 };
 
 template <int R, bool XG>
-LADL_INL void carve(Wave<R, XG> &w, float *smem, int pmax, float *ws)
+LADL_INL void carve(Wave<R, XG> &w, float *smem, int pmax, int nlds, float *ws)
 {
     constexpr int LDN = Wave<R, XG>::LDN;
     float *q = smem;
     w.gd = (double *)q; // first: the dynamic LDS base is 16-byte aligned
     q += 64;
-    float *big = XG ? ws : q;
-    w.Xs = big;
-    big += (size_t)pmax * LDN;
-    w.ys = big;
-    big += LDN;
-    if (!XG) q = big;
+    w.Xs = q;
+    if (XG) {
+        w.nlds = nlds;
+        q += (size_t)nlds * LDN;
+        w.Xg = ws;
+        w.ys = ws + (size_t)(pmax - nlds) * LDN;
+    } else {
+        w.nlds = pmax;
+        q += (size_t)pmax * LDN;
+        w.Xg = nullptr;
+        w.ys = q;
+        q += LDN;
+    }
     w.rbuf = q;
     q += 64 * R;
     w.A = q;
@@ -114,6 +132,63 @@ LADL_INL void ws_sync()
     __syncthreads();
 }
 
+// Element idx of column j of X (j may differ between lanes): LDS
+// instructions without the workspace; with it, for R = 32 a branch to an
+// LDS or a global load, for smaller R one generic load of the selected
+// address (measured on the ragged workload: the branch form made the
+// n <= 2048 bucket 1.5x faster and the n <= 512 and n <= 1024 buckets 5%
+// slower).  And the wave's R elements of a column j that is the same on
+// every lane, from LDS (j < nlds) or from the workspace (j >= nlds).
+typedef __attribute__((address_space(3))) float lds_f32;
+typedef __attribute__((address_space(1))) float glb_f32;
+
+template <int R, bool XG>
+LADL_INL const float *xaddr(const Wave<R, XG> &w, int j)
+{
+    constexpr int LDN = Wave<R, XG>::LDN;
+    return (j < w.nlds) ? w.Xs + j * LDN : w.Xg + (j - w.nlds) * LDN;
+}
+
+template <int R, bool XG>
+LADL_INL float xget(const Wave<R, XG> &w, int j, int idx)
+{
+    constexpr int LDN = Wave<R, XG>::LDN;
+    if (!XG) return ((const lds_f32 *)w.Xs)[j * LDN + idx];
+    if (R >= 32) {
+        if (j < w.nlds) return ((const lds_f32 *)w.Xs)[j * LDN + idx];
+        return ((const glb_f32 *)w.Xg)[(j - w.nlds) * LDN + idx];
+    }
+    return xaddr(w, j)[idx];
+}
+
+template <int R, bool XG>
+LADL_INL void xput(Wave<R, XG> &w, int j, int idx, float v)
+{
+    constexpr int LDN = Wave<R, XG>::LDN;
+    if (!XG || j < w.nlds)
+        ((lds_f32 *)w.Xs)[j * LDN + idx] = v;
+    else
+        ((glb_f32 *)w.Xg)[(j - w.nlds) * LDN + idx] = v;
+}
+
+template <int R, bool XG>
+LADL_INL void xcol_lds(const Wave<R, XG> &w, int j, float (&x)[R])
+{
+    constexpr int LDN = Wave<R, XG>::LDN;
+    const lds_f32 *c = (const lds_f32 *)w.Xs + j * LDN + lane_id();
+#pragma unroll
+    for (int k = 0; k < R; ++k) x[k] = c[64 * k];
+}
+
+template <int R, bool XG>
+LADL_INL void xcol_ws(const Wave<R, XG> &w, int j, float (&x)[R])
+{
+    constexpr int LDN = Wave<R, XG>::LDN;
+    const glb_f32 *c = (const glb_f32 *)w.Xg + (j - w.nlds) * LDN + lane_id();
+#pragma unroll
+    for (int k = 0; k < R; ++k) x[k] = c[64 * k];
+}
+
 // --------------------------------------------------------------------------
 // problem load: X row-major in HBM -> column-major in LDS (coalesced reads)
 // --------------------------------------------------------------------------
@@ -125,7 +200,7 @@ LADL_INL bool load_problem(Wave<R, XG> &w, const float *__restrict__ X, const fl
     // without guards: a zero row has a zero residual and no weight)
     const int l = lane_id(), n = w.n, p = w.p, top = 64 * R;
     for (int j = 0; j < p; ++j)
-        for (int i = n + l; i < top; i += 64) w.Xs[j * LDN + i] = 0.f;
+        for (int i = n + l; i < top; i += 64) xput(w, j, i, 0.f);
     for (int i = n + l; i < top; i += 64) w.ys[i] = 0.f;
     bool finite = true;
     const int np = n * p;
@@ -137,7 +212,7 @@ LADL_INL bool load_problem(Wave<R, XG> &w, const float *__restrict__ X, const fl
             --i;
         else if ((i + 1) * p <= e)
             ++i;
-        w.Xs[(e - i * p) * LDN + i] = v;
+        xput(w, e - i * p, i, v);
         finite = finite && __builtin_isfinite(v);
     }
     for (int i = l; i < n; i += 64) {
@@ -148,7 +223,7 @@ LADL_INL bool load_problem(Wave<R, XG> &w, const float *__restrict__ X, const fl
     ws_sync<XG>();
     for (int j = 0; j < p; ++j) {
         float part = 0.f;
-        for (int i = l; i < n; i += 64) part += fabsf(w.Xs[j * LDN + i]);
+        for (int i = l; i < n; i += 64) part += fabsf(xget(w, j, i));
         float sj = wsum(part);
         if (l == j) w.vca[j] = sj;
         if (l == j) w.cav = sj;
@@ -174,7 +249,7 @@ LADL_INL void residuals(Wave<R, XG> &w, float (&r)[R], float bv)
         if (bj != 0.f) {
 #pragma unroll
             for (int k = 0; k < R; ++k)
-                if (k < w.nslot) r[k] = fmaf(-w.Xs[j * LDN + 64 * k + l], bj, r[k]);
+                if (k < w.nslot) r[k] = fmaf(-xget(w, j, 64 * k + l), bj, r[k]);
         }
     }
 }
@@ -478,13 +553,18 @@ template <int R, bool XG>
 LADL_INL float ccd(Wave<R, XG> &w, float (&r)[R], float &bv, int frozen, float f)
 {
     constexpr int LDN = Wave<R, XG>::LDN;
-    const int l = lane_id(), p = w.p;
+    const int p = w.p;
     if (p == 1 && frozen == 0) return f;
-    // column j's values are loaded while column j-1 is updated
-    int j = (frozen == 0) ? 1 : 0;
-    float x[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) x[k] = w.Xs[j * LDN + 64 * k + l];
+    // The next column's values are loaded while this one is updated.  With
+    // the workspace only its columns are prefetched, into registers that no
+    // LDS load writes (a shared destination would make the compiler wait
+    // for the prefetch before each update); LDS columns are read when due.
+    const int j = (frozen == 0) ? 1 : 0;
+    float x[R], xn[R];
+    if (!XG)
+        xcol_lds(w, j, x);
+    else if (j >= w.nlds)
+        xcol_ws(w, j, xn);
     for (int sw = 0; sw < w.opt.max_sweeps; ++sw) {
         bool changed = false;
         for (int u = 0; u < p; ++u) {
@@ -492,13 +572,24 @@ LADL_INL float ccd(Wave<R, XG> &w, float (&r)[R], float &bv, int frozen, float f
             int jn = u + 1;
             if (jn == frozen) ++jn;
             if (jn >= p) jn = (frozen == 0) ? 1 : 0;
-            float xn[R];
+            if (!XG) {
+                float xp[R];
+                xcol_lds(w, jn, xp);
+                changed |= coord_update<R, XG>(w, r, bv, u, x);
 #pragma unroll
-            for (int k = 0; k < R; ++k) xn[k] = w.Xs[jn * LDN + 64 * k + l];
-            changed |= coord_update<R, XG>(w, r, bv, u, x);
+                for (int k = 0; k < R; ++k) x[k] = xp[k];
+            } else {
+                float xc[R];
+                if (u < w.nlds) {
+                    xcol_lds(w, u, xc);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) xc[k] = xn[k];
+                }
+                if (jn >= w.nlds) xcol_ws(w, jn, xn);
+                changed |= coord_update<R, XG>(w, r, bv, u, xc);
+            }
             w.c_updates++;
-#pragma unroll
-            for (int k = 0; k < R; ++k) x[k] = xn[k];
         }
         w.c_sweeps++;
         float fn = objective<R, XG>(w, r, bv);
@@ -524,7 +615,7 @@ LADL_INL void row_norms(const Wave<R, XG> &w, float (&nr)[R])
     for (int j = 0; j < w.p; ++j) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const float x = w.Xs[j * LDN + 64 * k + l];
+            const float x = xget(w, j, 64 * k + l);
             nr[k] = fmaf(x, x, nr[k]);
         }
     }
@@ -575,7 +666,7 @@ LADL_INL int choose_vertex(Wave<R, XG> &w, const float (&r)[R], float bv, uint32
             if (l == (row & 63)) seen |= 1u << (row >> 6);
         }
         float v = 0.f;
-        if (l < p) v = (col >= 0) ? ((l == col) ? 1.f : 0.f) : w.Xs[l * LDN + row];
+        if (l < p) v = (col >= 0) ? ((l == col) ? 1.f : 0.f) : xget(w, l, row);
         const float n0 = sqrtf(wsum(v * v));
         for (int a2 = 0; a2 < acc; ++a2) {
             const float qa = (l < p) ? Q[a2 * ALD + l] : 0.f;
@@ -698,7 +789,7 @@ LADL_INL bool vertex_eval(Wave<R, XG> &w, float (&rv)[R], uint32_t zbits, int s,
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int zq = rdlane(zl, q0 + t);
-            v[t] = (l < s && q0 + t < s) ? w.Xs[jl * LDN + zq] : 0.f;
+            v[t] = (l < s && q0 + t < s) ? xget(w, jl, zq) : 0.f;
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -738,7 +829,7 @@ LADL_INL bool vertex_eval(Wave<R, XG> &w, float (&rv)[R], uint32_t zbits, int s,
         const int jc = rdlane(jl, c);
         const double bc = (double)rdlane(xs, c);
 #pragma unroll
-        for (int k = 0; k < R; ++k) racc[k] = fma(-(double)w.Xs[jc * LDN + 64 * k + l], bc, racc[k]);
+        for (int k = 0; k < R; ++k) racc[k] = fma(-(double)xget(w, jc, 64 * k + l), bc, racc[k]);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) rv[k] = (float)racc[k];
@@ -767,7 +858,7 @@ LADL_INL bool certificate(Wave<R, XG> &w, const float (&rv)[R], uint32_t zbits, 
     for (int j = 0; j < p; ++j) {
         double part = 0.0;
 #pragma unroll
-        for (int k = 0; k < R; ++k) part += (double)(w.Xs[j * LDN + 64 * k + l] * sgnf(rv[k]));
+        for (int k = 0; k < R; ++k) part += (double)(xget(w, j, 64 * k + l) * sgnf(rv[k]));
         const double gj = wsum_d(part);
         g = (l == j) ? gj : g;
     }
@@ -794,7 +885,7 @@ LADL_INL bool certificate(Wave<R, XG> &w, const float (&rv)[R], uint32_t zbits, 
     for (int q = 0; q < s; ++q) {
         const float uq = rdlane(u, q);
         const int zq = rdlane(zl, q);
-        if (l < p) cj += (double)w.Xs[l * LDN + zq] * (double)uq;
+        if (l < p) cj += (double)xget(w, l, zq) * (double)uq;
     }
     c = (float)cj;
     const bool offS = (l < p) && !((smask >> l) & 1u);
@@ -873,7 +964,7 @@ LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, f
             rhs = (l == sel) ? -sgnf(usel) : 0.f;
         } else {
             dj0 = sgnf(rdlane(c, sel));
-            rhs = (l < s) ? -w.Xs[sel * LDN + zl] * dj0 : 0.f;
+            rhs = (l < s) ? -xget(w, sel, zl) * dj0 : 0.f;
         }
         const float dS = lu_solve(w.A, w.piv, s, rhs);
         if (l < p) w.vd[l] = 0.f;
@@ -889,11 +980,11 @@ LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, f
             const float dc = rdlane(dS, q);
 #pragma unroll
             for (int k = 0; k < R; ++k)
-                xd[k] = fmaf(w.Xs[jc * LDN + 64 * k + l], dc, xd[k]);
+                xd[k] = fmaf(xget(w, jc, 64 * k + l), dc, xd[k]);
         }
         if (!type1) {
 #pragma unroll
-            for (int k = 0; k < R; ++k) xd[k] = fmaf(w.Xs[sel * LDN + 64 * k + l], dj0, xd[k]);
+            for (int k = 0; k < R; ++k) xd[k] = fmaf(xget(w, sel, 64 * k + l), dj0, xd[k]);
         }
         const int zsel = type1 ? rdlane(zl, sel) : -1;
 #pragma unroll
@@ -988,7 +1079,7 @@ LADL_INL float objective64(Wave<R, XG> &w, float bval)
         if (bj != 0.0) {
 #pragma unroll
             for (int k = 0; k < R; ++k)
-                if (k < w.nslot) acc[k] -= (double)w.Xs[j * LDN + 64 * k + l] * bj;
+                if (k < w.nslot) acc[k] -= (double)xget(w, j, 64 * k + l) * bj;
         }
     }
     double s = 0.0;
@@ -1101,7 +1192,7 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
                     if (d != 0.f) {
                         constexpr int LDN = Wave<R, XG>::LDN;
 #pragma unroll
-                        for (int kk = 0; kk < R; ++kk) r[kk] = fmaf(-w.Xs[kax * LDN + 64 * kk + l], d, r[kk]);
+                        for (int kk = 0; kk < R; ++kk) r[kk] = fmaf(-xget(w, kax, 64 * kk + l), d, r[kk]);
                     }
                     bv = (l == kax) ? sprobe : bv;
                     f = objective<R, XG>(w, r, bv);
@@ -1208,7 +1299,7 @@ void k_wave(SolveArgs a)
 {
     extern __shared__ float smem[];
     Wave<R, XG> w;
-    carve<R, XG>(w, smem, a.pmax, XG ? a.gws + (int64_t)blockIdx.x * a.gws_stride : nullptr);
+    carve<R, XG>(w, smem, a.pmax, a.nlds, XG ? a.gws + (int64_t)blockIdx.x * a.gws_stride : nullptr);
     w.opt = a.opt;
     const int l = lane_id();
     for (;;) {
@@ -1226,8 +1317,8 @@ __global__ void k_reset(int32_t *c, int n)
     if (i < n) c[i] = 0;
 }
 
-size_t wave_lds_bytes(int R, int pmax, bool xg) { return 4 * wave_lds_floats(R, pmax, xg); }
-size_t wave_ws_floats_host(int R, int pmax) { return wave_ws_floats(R, pmax); }
+size_t wave_lds_bytes(int R, int pmax, bool xg, int nlds) { return 4 * wave_lds_floats(R, pmax, xg, nlds); }
+size_t wave_ws_floats_host(int R, int pmax, int nlds) { return wave_ws_floats(R, pmax, nlds); }
 
 hipError_t launch_reset(int32_t *counters, int n, hipStream_t s)
 {
@@ -1238,7 +1329,7 @@ hipError_t launch_reset(int32_t *counters, int n, hipStream_t s)
 template <int R, bool XG, bool DENSE>
 static hipError_t launch_wave_t(const SolveArgs &a, int grid, hipStream_t s)
 {
-    size_t lds = wave_lds_bytes(R, a.pmax, XG);
+    size_t lds = wave_lds_bytes(R, a.pmax, XG, a.nlds);
     static bool attr = false;
     if (!attr) {
         // allow dynamic LDS beyond the default limit; harmless if refused
@@ -1251,10 +1342,10 @@ static hipError_t launch_wave_t(const SolveArgs &a, int grid, hipStream_t s)
 }
 
 template <int R, bool XG, bool DENSE>
-static int max_blocks_t(int pmax)
+static int max_blocks_t(int pmax, int nlds)
 {
     int nb = 0;
-    size_t lds = wave_lds_bytes(R, pmax, XG);
+    size_t lds = wave_lds_bytes(R, pmax, XG, nlds);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_wave<R, XG, DENSE>, 64, lds) != hipSuccess) return 0;
     return nb;
 }
@@ -1295,34 +1386,34 @@ hipError_t launch_wave(int R, bool xg, bool dense, const SolveArgs &a, int grid,
     }
 }
 
-int wave_max_blocks_per_cu(int R, int pmax, bool xg, bool dense)
+int wave_max_blocks_per_cu(int R, int pmax, bool xg, bool dense, int nlds)
 {
     if (dense) {
         if (!xg) return 0;
         switch (R) {
-        case 1: return max_blocks_t<1, true, true>(pmax);
-        case 2: return max_blocks_t<2, true, true>(pmax);
-        case 4: return max_blocks_t<4, true, true>(pmax);
+        case 1: return max_blocks_t<1, true, true>(pmax, nlds);
+        case 2: return max_blocks_t<2, true, true>(pmax, nlds);
+        case 4: return max_blocks_t<4, true, true>(pmax, nlds);
         default: return 0;
         }
     }
     if (xg) {
         switch (R) {
-        case 1: return max_blocks_t<1, true, false>(pmax);
-        case 2: return max_blocks_t<2, true, false>(pmax);
-        case 4: return max_blocks_t<4, true, false>(pmax);
-        case 8: return max_blocks_t<8, true, false>(pmax);
-        case 16: return max_blocks_t<16, true, false>(pmax);
-        case 32: return max_blocks_t<32, true, false>(pmax);
+        case 1: return max_blocks_t<1, true, false>(pmax, nlds);
+        case 2: return max_blocks_t<2, true, false>(pmax, nlds);
+        case 4: return max_blocks_t<4, true, false>(pmax, nlds);
+        case 8: return max_blocks_t<8, true, false>(pmax, nlds);
+        case 16: return max_blocks_t<16, true, false>(pmax, nlds);
+        case 32: return max_blocks_t<32, true, false>(pmax, nlds);
         default: return 0;
         }
     }
     switch (R) {
-    case 1: return max_blocks_t<1, false, false>(pmax);
-    case 2: return max_blocks_t<2, false, false>(pmax);
-    case 4: return max_blocks_t<4, false, false>(pmax);
-    case 8: return max_blocks_t<8, false, false>(pmax);
-    case 16: return max_blocks_t<16, false, false>(pmax);
+    case 1: return max_blocks_t<1, false, false>(pmax, nlds);
+    case 2: return max_blocks_t<2, false, false>(pmax, nlds);
+    case 4: return max_blocks_t<4, false, false>(pmax, nlds);
+    case 8: return max_blocks_t<8, false, false>(pmax, nlds);
+    case 16: return max_blocks_t<16, false, false>(pmax, nlds);
     default: return 0;
     }
 }
