@@ -40,11 +40,12 @@ __host__ __device__ constexpr int wave_ldn(int R) { return 64 * R + 1; }
 
 // LDS floats per wave: gd, [Xs, ys when resident; the first nlds columns
 // of Xs with the workspace], best residuals, A (pmax rows), A0, 6 vectors,
-// sa/sw, zs/ss/piv
+// sa/sw, zs/ss/piv, the chop state
+constexpr int CHOP_FLOATS = 32;
 __host__ __device__ constexpr size_t wave_lds_floats(int R, int pmax, bool xg, int nlds)
 {
     return 64 + (size_t)(xg ? nlds : pmax + 1) * wave_ldn(R) + 64 * (size_t)R + (size_t)pmax * ALD +
-           (size_t)pmax * (pmax + 1) + 6 * 32 + 128 + 3 * 32;
+           (size_t)pmax * (pmax + 1) + 6 * 32 + 128 + 3 * 32 + CHOP_FLOATS;
 }
 // global workspace floats per wave with the workspace: columns nlds .. p-1
 // of Xs, then ys
@@ -62,6 +63,9 @@ struct Wave {
     float *Xs, *Xg, *ys, *rbuf, *A, *A0, *vb, *vbb, *vca, *vd, *vg, *vt, *sa, *sw;
     double *gd;
     int *zs, *ss, *piv;
+    // the ternary chop's state (wave-uniform): kept in LDS rather than in
+    // VGPRs that would be live across every probe's CCD
+    Chop *chop;
     int n, p, nslot, a0ld, nlds;
     float lam, ynorm1;
     float cav; // lane j: sum_i |x_ij|
@@ -117,6 +121,8 @@ LADL_INL void carve(Wave<R, XG> &w, float *smem, int pmax, int nlds, float *ws)
     w.ss = (int *)q;
     q += 32;
     w.piv = (int *)q;
+    q += 32;
+    w.chop = (Chop *)q;
 }
 
 // After this wave writes its workspace (global memory when XG): the stores
@@ -1111,7 +1117,8 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
     else if (a.b_init)
         b0 = (l < p) ? a.b_init[a.b_off[s] + l] : 0.f;
     float bv = (l < p && __builtin_isfinite(b0)) ? b0 : 0.f; // lane j holds b_j
-    float bbv = bv;                                           // best point of the chop
+    // the chop's best point b lives in LDS (vbb, lane j < 32: b_j), like its
+    // residuals (rbuf): a register copy would be live across every probe
     float r[R], rv[R];
     for (int t = a.t0; t < a.t1; ++t) {
         const int64_t o = (int64_t)s * a.path_len + t;
@@ -1137,7 +1144,8 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
             const bool snap = !(w.opt.flags & FLAG_NO_SNAP);
             const int rounds = (p < 2) ? 0 : ((w.opt.max_rounds < 0) ? p : w.opt.max_rounds);
             const float B = (w.lam > 0.f) ? w.ynorm1 / w.lam : FINF;
-            Chop q;
+            static_assert(sizeof(Chop) <= 4 * CHOP_FLOATS, "chop state does not fit its LDS slot");
+            Chop &q = *w.chop;
             int phase = 0; // 0: unrestricted CCD done, 1: a chop probe done
             int frozen = -1, round = 0, kax = 0;
             float fbest = FINF;
@@ -1167,28 +1175,28 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
                         kax = (kax + 1) % p;
                     }
                     ++round;
-                    bbv = bv;
+                    if (l < 32) w.vbb[l] = bv;
 #pragma unroll
                     for (int kk = 0; kk < R; ++kk) w.rbuf[64 * kk + l] = r[kk];
                     fbest = f;
-                    chop_init(q, rdlane(bbv, kax), f, B, w.opt.chop_range);
+                    chop_init(q, rdlane(bv, kax), f, B, w.opt.chop_range);
                     more = chop_next(q, 0.f, sprobe, w.opt);
                 } else {
                     w.c_probes++;
                     if (f < fbest) {
                         fbest = f;
-                        bbv = bv;
+                        if (l < 32) w.vbb[l] = bv;
 #pragma unroll
                         for (int kk = 0; kk < R; ++kk) w.rbuf[64 * kk + l] = r[kk];
                     }
                     more = chop_next(q, f, sprobe, w.opt);
                 }
                 // next CCD starts from the best point; a probe sets b_kax := s
-                bv = bbv;
+                bv = (l < 32) ? w.vbb[l] : 0.f;
 #pragma unroll
                 for (int kk = 0; kk < R; ++kk) r[kk] = w.rbuf[64 * kk + l];
                 if (more) {
-                    const float d = sprobe - rdlane(bbv, kax);
+                    const float d = sprobe - rdlane(bv, kax);
                     if (d != 0.f) {
                         constexpr int LDN = Wave<R, XG>::LDN;
 #pragma unroll
