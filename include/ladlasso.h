@@ -91,11 +91,15 @@ typedef struct {
                             wave, else in an HBM workspace, and for
                             n <= 256 with more than two grids' worth of
                             solves the HBM workspace with the kernel
-                            variant built for 5 waves per SIMD
+                            variant built for 4 waves per SIMD
                             (ladl_autotune may change the choice);
                             0: the HBM workspace for every bucket;
-                            1: as 0, with the 5-wave variant wherever
-                            n <= 256                          (default -1)    */
+                            1: as 0, with the 4-wave variant wherever
+                            n <= 256.  With the workspace, the leading
+                            columns of X that fit the LDS left over at
+                            the kernel's occupancy stay in LDS (when the
+                            plan has one bucket, or for n > 1024)
+                                                              (default -1)    */
     float chop_range;    /* initial half-width of the chop's range around
                             b_k, as a fraction of max(1, |b_k|); the range
                             is doubled while an end is lower than the
@@ -218,7 +222,7 @@ int ladl_graph_destroy(ladl_graph_t graph);
  * Time each candidate schedule on this plan's own data (runs the solve
  * several times on `stream`, synchronously) and keep the fastest per
  * bucket in the plan: X resident in LDS, X in the HBM workspace, and (for
- * n <= 256) X in the HBM workspace with the 5-waves-per-SIMD kernel
+ * n <= 256) X in the HBM workspace with the 4-waves-per-SIMD kernel
  * variant, for the buckets where more than one exists.  The choice is
  * cached in the file named by the environment variable LADL_TUNE_CACHE (if
  * set), keyed by device, rows per lane and p_max.  Optional: plans start

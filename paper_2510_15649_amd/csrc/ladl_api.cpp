@@ -61,7 +61,7 @@ struct Bucket {
     int offset = 0, count = 0; // slice of the order array
     int grid = 0;
     bool xg = false;           // X in the global workspace instead of LDS
-    bool dense = false;        // the kernel variant built for 5 waves per SIMD
+    bool dense = false;        // the kernel variant built for 4 waves per SIMD
     int nlds = 0;              // with the workspace: columns of X kept in LDS
     int per_cu = 0;
     int64_t ws_off = 0;        // this bucket's slice of the workspace
@@ -333,7 +333,7 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         set_schedule(pl, b, xg);
         // the dense variant where the bucket holds more than DENSE_MIN_ROUNDS
         // full grids of solves: the extra waves then shorten every round
-        // (c1, 8192 solves of n = 200, p = 8: 3.77 instead of 4.04 ms)
+        // (c1, 8192 solves of n = 200, p = 8: 3.82 instead of 4.0 ms)
         if (wave_has_dense(R) && (o.schedule == 1 || (o.schedule == -1 && b.count > DENSE_MIN_ROUNDS * b.grid)))
             set_schedule(pl, b, true, true);
         pl->buckets.push_back(b);

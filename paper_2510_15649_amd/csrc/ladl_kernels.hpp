@@ -75,7 +75,7 @@ struct BruteArgs {
 // host-side launchers (defined in ladl_kernels.hip)
 // wave kernel: R = row slots per lane (1..32); xg = X held in a per-wave
 // global workspace instead of LDS (required for R = 32), except its first
-// nlds columns; dense = the variant compiled for 5 waves per SIMD (R <= 4
+// nlds columns; dense = the variant compiled for 4 waves per SIMD (R <= 4
 // with xg only)
 size_t wave_lds_bytes(int R, int pmax, bool xg, int nlds);
 size_t wave_ws_floats_host(int R, int pmax, int nlds);

@@ -1290,15 +1290,18 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
     }
 }
 
-// Register budget.  Left to the compiler, the R <= 4 kernels take 124-144
-// VGPRs (3-4 waves per SIMD), most of it live only in the vertex, chop and
-// finisher code.  The DENSE variant asks for 5 waves per SIMD (96 VGPRs):
-// the compiler then spills a few values of the per-probe chop logic, and the
-// coordinate-update loop stays spill-free.  It only pays where the X
-// workspace is in HBM (LDS would cap the waves first) and the bucket has
-// solves enough to fill the extra waves; for R >= 8 the spills reach the
-// update loop (the n <= 1024 bucket ran 1.5-2x slower), so it is not built.
-constexpr int DENSE_WAVES_PER_SIMD = 5;
+// Register budget.  Left to the compiler, the R <= 4 kernels take 124-135
+// VGPRs (3 waves per SIMD), most of it live only in the vertex and
+// finisher code.  The DENSE variant asks for 4 waves per SIMD (128 VGPRs);
+// the coordinate-update loop stays spill-free.  It only pays where the X
+// workspace is in HBM (with all of X in LDS the LDS caps the waves first)
+// and the bucket has solves enough to fill the extra waves.  Measured on
+// c1 (n = 200, p = 8, 8192 solves): 4 waves per SIMD keep 5 of the 8
+// columns in LDS and the rest in L2 (0.3 GB of HBM traffic per launch,
+// 3.82 ms); 5 waves keep 3 columns in LDS, miss L2 (1.8 GB, 4.0 ms).  For
+// R >= 8 the budget makes the update loop spill (the n <= 1024 bucket ran
+// 1.5-2x slower), so it is not built.
+constexpr int DENSE_WAVES_PER_SIMD = 4;
 __host__ __device__ constexpr int waves_per_eu(bool dense) { return dense ? DENSE_WAVES_PER_SIMD : 1; }
 
 template <int R, bool XG, bool DENSE>

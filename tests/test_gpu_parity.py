@@ -82,7 +82,7 @@ def test_schedules(torch, opts):
 
 def test_dense_variant_ragged(torch):
     """Ragged row subsets with every bucket in the HBM workspace and the
-    5-waves-per-SIMD kernel variant for n <= 256."""
+    4-waves-per-SIMD kernel variant for n <= 256."""
     w = W.config2(num_subsets=160)
     plan, g = gpu_solve(torch, w, schedule=1)
     desc = plan.describe()
