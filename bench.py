@@ -346,6 +346,11 @@ def main():
         cpu = {"value": k * w.path_len / r["seconds"], "unit": "solves/s", "cores": threads, "kind": "oracle",
                "sample": f"{k} of {w.num_solves} solves (uniform, seeded); FP64 C oracle with the same schedule "
                          f"(max_rounds={args.max_rounds}); {r['seconds']:.1f} s on {threads} threads"}
+        # the same oracle on one host thread, on the first quarter of that sample
+        k1 = max(1, k // 4)
+        r1 = O.solve_batch(w, nthreads=1, solves=solves[:k1], **opts)
+        cpu["one_thread"] = {"value": k1 * w.path_len / r1["seconds"], "unit": "solves/s",
+                             "sample": f"{k1} of the sampled solves; {r1['seconds']:.1f} s on 1 thread"}
 
     secondary = []
     backward = main_backward
