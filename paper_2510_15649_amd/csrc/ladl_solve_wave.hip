@@ -201,7 +201,6 @@ LADL_INL void xcol_ws(const Wave<R, XG> &w, int j, float (&x)[R])
 template <int R, bool XG>
 LADL_INL bool load_problem(Wave<R, XG> &w, const float *__restrict__ X, const float *__restrict__ y)
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
     // rows n .. 64R-1 are zero padding (so hot loops read all R slots
     // without guards: a zero row has a zero residual and no weight)
     const int l = lane_id(), n = w.n, p = w.p, top = 64 * R;
@@ -246,7 +245,6 @@ LADL_INL bool load_problem(Wave<R, XG> &w, const float *__restrict__ X, const fl
 template <int R, bool XG>
 LADL_INL void residuals(Wave<R, XG> &w, float (&r)[R], float bv)
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id();
 #pragma unroll
     for (int k = 0; k < R; ++k) r[k] = (k < w.nslot) ? w.ys[64 * k + l] : 0.f;
@@ -290,7 +288,6 @@ struct Sel {
 template <int R, bool XG>
 LADL_INL Sel owner_of(const float (&a)[R], float av, float m)
 {
-    const int l = lane_id();
     int myslot = -1;
 #pragma unroll
     for (int k = R - 1; k >= 0; --k)
@@ -558,7 +555,6 @@ LADL_INL bool coord_update(Wave<R, XG> &w, float (&r)[R], float &bv, int j, cons
 template <int R, bool XG>
 LADL_INL float ccd(Wave<R, XG> &w, float (&r)[R], float &bv, int frozen, float f)
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
     const int p = w.p;
     if (p == 1 && frozen == 0) return f;
     // The next column's values are loaded while this one is updated.  With
@@ -614,7 +610,6 @@ LADL_INL float ccd(Wave<R, XG> &w, float (&r)[R], float &bv, int frozen, float f
 template <int R, bool XG>
 LADL_INL void row_norms(const Wave<R, XG> &w, float (&nr)[R])
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id();
 #pragma unroll
     for (int k = 0; k < R; ++k) nr[k] = 0.f;
@@ -639,7 +634,6 @@ LADL_INL void row_norms(const Wave<R, XG> &w, float (&nr)[R])
 template <int R, bool XG>
 LADL_INL int choose_vertex(Wave<R, XG> &w, const float (&r)[R], float bv, uint32_t &zbits)
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id(), p = w.p;
     float dist[R];
     row_norms<R, XG>(w, dist);
@@ -783,7 +777,6 @@ LADL_INL float lu_solve_t(const float *A, const int *piv, int s, float v)
 template <int R, bool XG>
 LADL_INL bool vertex_eval(Wave<R, XG> &w, float (&rv)[R], uint32_t zbits, int s, float &f)
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id(), a0ld = w.a0ld;
     // lane q < s: row Z_q and column S_q, held in registers so that the
     // gathers below issue independent loads
@@ -854,7 +847,6 @@ template <int R, bool XG>
 LADL_INL bool certificate(Wave<R, XG> &w, const float (&rv)[R], uint32_t zbits, int s, float &u, float &c,
                             bool &unique)
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id(), p = w.p, a0ld = w.a0ld;
     const int zl = (l < s) ? w.zs[l] : 0;
     const int jl = (l < s) ? w.ss[l] : 0;
@@ -920,7 +912,6 @@ template <int R, bool XG>
 LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, float &f, float &u, float &c,
                       bool &unique, int maxp)
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id(), p = w.p;
     const float lam = w.lam;
     float fprev = FINF;
@@ -1075,7 +1066,6 @@ LADL_INL void perturb_y(Wave<R, XG> &w)
 template <int R, bool XG>
 LADL_INL float objective64(Wave<R, XG> &w, float bval)
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
     const int l = lane_id();
     double acc[R];
 #pragma unroll
@@ -1198,7 +1188,6 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
                 if (more) {
                     const float d = sprobe - rdlane(bv, kax);
                     if (d != 0.f) {
-                        constexpr int LDN = Wave<R, XG>::LDN;
 #pragma unroll
                         for (int kk = 0; kk < R; ++kk) r[kk] = fmaf(-xget(w, kax, 64 * kk + l), d, r[kk]);
                     }
