@@ -150,7 +150,8 @@ void ladl_default_options(ladl_options *opt);
  * (n_k * p_k, then increasing lambda when lambda_hint is given) for the
  * persistent work queue, and the schedule chosen.  The plan owns device
  * memory: the metadata, the queue counters, a workspace for buckets whose X
- * does not fit LDS, and (when every problem is used by exactly one solve)
+ * is not held in LDS (all or part of it, per the schedule), and (when every
+ * problem is used by exactly one solve)
  * 128 bytes per solve for the backward.  Calls on one plan share these, so
  * calls on the same plan must not run concurrently on different streams;
  * calls in stream order are fine.

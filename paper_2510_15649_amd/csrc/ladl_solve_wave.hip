@@ -1,5 +1,6 @@
 // Forward LAD-LASSO solve: one wavefront per solve, persistent grid with an
-// atomic work queue, problem data resident in LDS.
+// atomic work queue, problem data in LDS (or partly in a per-wave HBM
+// workspace for the larger buckets).
 //
 // Per solve (Abstract; Sections 3.3-3.6 of the paper, plus a vertex
 // certificate and simplex finisher that the paper does not have):
