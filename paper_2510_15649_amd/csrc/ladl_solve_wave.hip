@@ -1291,11 +1291,20 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
 // 3.82 ms); 5 waves keep 3 columns in LDS, miss L2 (1.8 GB, 4.0 ms).  For
 // R >= 8 the budget makes the update loop spill (the n <= 1024 bucket ran
 // 1.5-2x slower), so it is not built.
+// R = 32 left to the compiler takes 256 VGPRs plus 152 accumulation
+// registers, one wave per SIMD; it is compiled for 2 waves per SIMD (256
+// registers, some spilled to scratch), which lets the second wave hide the
+// first one's latency: 6144 problems of n > 1024 on their 32-lambda paths
+// take 0.90 instead of 1.21 s.
 constexpr int DENSE_WAVES_PER_SIMD = 4;
-__host__ __device__ constexpr int waves_per_eu(bool dense) { return dense ? DENSE_WAVES_PER_SIMD : 1; }
+constexpr int R32_WAVES_PER_SIMD = 2;
+__host__ __device__ constexpr int waves_per_eu(int R, bool dense)
+{
+    return dense ? DENSE_WAVES_PER_SIMD : (R >= 32 ? R32_WAVES_PER_SIMD : 1);
+}
 
 template <int R, bool XG, bool DENSE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_eu(DENSE))))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R, DENSE))))
 void k_wave(SolveArgs a)
 {
     extern __shared__ float smem[];
