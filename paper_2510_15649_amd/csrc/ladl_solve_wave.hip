@@ -1295,12 +1295,16 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
 // registers, one wave per SIMD; it is compiled for 2 waves per SIMD (256
 // registers, some spilled to scratch), which lets the second wave hide the
 // first one's latency: 6144 problems of n > 1024 on their 32-lambda paths
-// take 0.90 instead of 1.21 s.
+// take 0.90 instead of 1.21 s.  R = 8 (170 VGPRs, 2 waves) is compiled for
+// 3 (168 VGPRs, no spill in the update loop): 6144 problems of n in
+// (256, 512] 0.315 -> 0.301 s.  R = 16 at 3 waves spills in the update loop
+// and ran 16% slower, so it keeps the compiler's 2.
 constexpr int DENSE_WAVES_PER_SIMD = 4;
 constexpr int R32_WAVES_PER_SIMD = 2;
+constexpr int R8_WAVES_PER_SIMD = 3;
 __host__ __device__ constexpr int waves_per_eu(int R, bool dense)
 {
-    return dense ? DENSE_WAVES_PER_SIMD : (R >= 32 ? R32_WAVES_PER_SIMD : 1);
+    return dense ? DENSE_WAVES_PER_SIMD : (R >= 32 ? R32_WAVES_PER_SIMD : (R == 8 ? R8_WAVES_PER_SIMD : 1));
 }
 
 template <int R, bool XG, bool DENSE>
