@@ -355,7 +355,8 @@ def main():
     secondary = []
     backward = main_backward
     if not args.no_secondary:
-        for cfg, mr, fl in [("c1", 0, 0), ("c1", 1, L.FLAG_GOLDEN), ("c2", 1, 0), ("c2", 0, 0), ("c4s", 1, 0)]:
+        for cfg, mr, fl in [("c1", 0, 0), ("c1", 1, L.FLAG_GOLDEN), ("c2", 1, 0), ("c2", 0, 0), ("c3", 1, 0),
+                            ("c4s", 1, 0)]:
             if cfg == args.config and mr == args.max_rounds and fl == flags:
                 continue
             log(f"generating workload {cfg}")
@@ -369,6 +370,9 @@ def main():
                 entry["graph_ms_per_step"], bw = path_graph_and_backward(L, torch, ws, s)
                 bw["traffic"] = recorded_traffic("c4_sample_kernel_stats.md", "backward_traffic_bytes_per_launch")
                 backward = backward or bw
+            elif cfg == "c3":
+                # the differentiation workload: its backward (dL/dy, dL/dX of all 1024 problems)
+                _, entry["backward"] = path_graph_and_backward(L, torch, ws, s)
             secondary.append(entry)
         secondary.append(measure_cv(L, torch))
         secondary.append(measure_brute(L, torch))
