@@ -59,7 +59,9 @@ enum {
     LADL_MAXITER = 2,      /* finisher pivot cap reached before certifying   */
     LADL_NONFINITE = 3,    /* NaN or Inf in this problem's X or y            */
     LADL_BADLAMBDA = 4,    /* lambda < 0 or NaN                              */
-    LADL_NOTCERTIFIED = 5  /* singular vertex system: best point returned    */
+    LADL_NOTCERTIFIED = 5  /* no certificate: a singular vertex system, or
+                              the finisher (and its perturbed retry) ended
+                              without one; the best point is returned       */
 };
 
 /* option flags */
