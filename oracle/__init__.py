@@ -289,7 +289,7 @@ def cv(X, y, lams, folds: int, fold_of_row=None, **opts):
             b, info = solve(X[tr], y[tr], lams[t], b_init=b, **opts)
             bs[f, t] = b
             err[f, t] = float(np.sum(np.abs(y[va] - X[va] @ b)))
-            uniq[f, t] = bool(info["unique"]) and info["margin_uc"] >= 1e-3 and info["margin_r"] >= 1e-6
+            uniq[f, t] = bool(info["unique"]) and info["margin_uc"] >= 1e-4 and info["margin_r"] >= 4e-6
     curve = err.sum(axis=0)
     return dict(err=err, unique=uniq, cv=curve, best=int(np.argmin(curve)), b=bs)
 

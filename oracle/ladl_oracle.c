@@ -422,7 +422,7 @@ static int vertex_solve(const orc_prob *P, const overt *V, olu *L, double *A, do
 
 typedef struct {
     int certified, unique;
-    double umax, cmax, gap, f, cond, margin_u, margin_c, margin_r;
+    double umax, cmax, gap, f, cond, margin_u, margin_c, margin_cz, margin_r;
 } ocert;
 
 static double sgn(double v) { return (v > 0.0) - (v < 0.0); }
@@ -461,13 +461,18 @@ static void certificate(const orc_prob *P, double lam, const overt *V, const olu
     int ok = C->umax <= 1.0 + 1e-9;
     C->cmax = -lam;
     C->margin_c = 1.0;
+    C->margin_cz = 1.0;
     for (int j = 0; j < p; ++j) {
         if (inS[j]) continue;
-        double colabs = 0.0;
+        double colabs = 0.0, colz = 0.0;
         for (int i = 0; i < n; ++i) colabs += fabs(XIJ(P, i, j));
+        for (int q = 0; q < s; ++q) colz += fabs(XIJ(P, V->Z[q], j));
         C->cmax = fmax(C->cmax, fabs(c[j]) - lam);
         if (fabs(c[j]) > lam + 1e-9 * (lam + colabs)) ok = 0;
         C->margin_c = fmin(C->margin_c, (lam - fabs(c[j])) / (lam + colabs));
+        /* the same slack against the terms that carry the error of the
+           vertex rows' duals u_Z into c_j = sum_i x_ij u_i */
+        C->margin_cz = fmin(C->margin_cz, (lam - fabs(c[j])) / (lam + colz));
     }
     /* distance of the other rows from their hyperplanes */
     C->margin_r = INFINITY;
@@ -499,7 +504,7 @@ static void fill_info(const orc_prob *P, const overt *V, const double *b, const 
     I->umax = C->umax;
     I->cmax = C->cmax;
     I->gap = C->gap;
-    I->margin_uc = fmin(C->margin_u, C->margin_c);
+    I->margin_uc = fmin(C->margin_u, C->margin_cz);
     I->margin_r = C->margin_r;
     I->nS = 0;
     I->S_mask = 0;
@@ -600,6 +605,7 @@ int orc_certify(const orc_prob *P, double lambda, double *b, double *u, orc_info
 /*                                                                           */
 /* F(s): from the best point found so far, set b_k := s and run CCD with     */
 /* axis k frozen (the restricted sub-search); F(s) is the objective reached. */
+/* The centre c = b_k is probed too.                                         */
 /* The initial range c +- h, h = chop_range * max(1,|c|), around the current */
 /* b_k (the paper leaves the initial range to the user and extends it until  */
 /* it holds the minimum, Section 3.6) is doubled outward while an end point */
@@ -651,7 +657,10 @@ static void ternary(otern *T)
     double c = T->b[T->k];
     double h = T->o->chop_range * fmax(1.0, fabs(c));
     double lo = fmax(c - h, -B), hi = fmin(c + h, B);
-    double Fc = T->f;
+    /* the centre is probed like the ends: the point the chop starts from
+     * lies on the locus of axis-wise minima only if the CCD before it ran
+     * to convergence, and a sweep cap can stop it short */
+    double Fc = probe(T, c);
     double Flo = probe(T, lo), Fhi = probe(T, hi);
     int ext = 0;
     while (Flo < Fc && lo > -B && ext < 64) {

@@ -67,7 +67,9 @@ typedef struct {
     double umax;       /* max_{i in Z} |u_i|                                     */
     double cmax;       /* max_{j not in S} |c_j| - lambda   (<= 0 when feasible) */
     double gap;        /* f(b) - y.u (LP duality gap)                            */
-    double margin_uc;  /* min(1 - max|u_Z|, min_{j not in S} (lambda-|c_j|)/(lambda+sum_i|x_ij|)) */
+    double margin_uc;  /* min(1 - max|u_Z|, min_{j not in S} (lambda-|c_j|)/(lambda+sum_{i in Z}|x_ij|)):
+                          the dual slacks against the size of the terms through
+                          which an error of u_Z enters them                  */
     double margin_r;   /* min over rows off Z of |r_i| / (|y_i| + sum_j |x_ij b_j|) */
     long sweeps, updates, probes, pivots;
     double f_ccd;      /* objective after the first CCD                          */

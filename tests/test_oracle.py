@@ -220,6 +220,25 @@ def test_p2_ternary_chop_exact_without_finisher():
         assert abs(f_np(X, y, lam, b) - fb) <= 1e-9 * max(1, fb)
 
 
+def test_p2_chop_exact_after_a_capped_first_ccd():
+    """The chop must reach the optimum also when the coordinate descent before
+    it stops at its sweep cap, short of an axis-wise minimum (correlated
+    columns make it zig-zag): the chop then probes the centre of its first
+    range, since the start point is not on the locus of axis-wise minima."""
+    rng = np.random.default_rng(31)
+    for i in range(80):
+        n = int(rng.integers(3, 60))
+        X = rng.standard_normal((n, 2))
+        X[:, 1] = 0.9 * X[:, 0] + 0.3 * X[:, 1]
+        y = X @ rng.uniform(-3, 3, 2) + rng.laplace(0, 1, n)
+        lam = float(10 ** rng.uniform(-2, 1))
+        fb, _, _ = O.brute_force(X, y, lam)
+        for sweeps in (1, 2, 8):
+            b, info = O.solve(X, y, lam, use_finisher=0, max_rounds=1, max_sweeps=sweeps, tol_f=1e-6)
+            assert info["certified"], (i, sweeps)
+            assert abs(f_np(X, y, lam, b) - fb) <= 1e-9 * max(1, fb), (i, sweeps)
+
+
 def test_stuck_point_rescued_by_ternary_chop():
     """Plain CCD stops at an axis-wise minimum above the optimum (Section
     3.4); the ternary chop along the locus (Sections 3.5-3.6) reaches it."""
