@@ -3,10 +3,18 @@
 One step = one forward pass of the whole solve path (cyclical coordinate
 descent with exact weighted-median coordinate updates, ternary chop along
 the locus of axis-wise minima, vertex snap and optimality certificate,
-edge-descent finisher) over one batch.  The headline workload is 512
-problems (n=200, p=8) x 16 lambdas = 8192 solves with the paper's schedule
-(one ternary-chop round).  Inputs are resident in HBM before timing starts.
-Prints one JSON line.
+edge-descent finisher) over one batch.  The headline workload is the large
+ragged batch: 65536 problems, n ~ U[32, 2048], p ~ U[4, 32], each solved
+along a warm-started 32-value lambda path in one persistent launch per
+bucket (2,097,152 solves per step).  Inputs are resident in HBM before
+timing starts.  Prints one JSON line.
+
+Secondary lines: 512 problems x 16 lambdas with the plain one-thread-per-
+solve kernel beside the wave kernel (the speed-up claim), the 4096 row
+subsets of one correlated dataset (achieved HBM GB/s against the peak), the
+differentiation workload with its backward, the ragged batch's lambda path
+as a HIP graph and its backward against the HBM roofline, K-fold
+cross-validation and vertex enumeration.
 """
 import argparse
 import hashlib
@@ -23,30 +31,25 @@ sys.path.insert(0, ROOT)
 sys.path.insert(0, os.path.join(ROOT, "tests"))
 
 PEAK_HBM_GBS = 8000.0
-# fp32 VALU lane-ops/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (an FMA counted once)
+# fp32 VALU lane-ops/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, every lane
+# operation counted once (157.3 TFLOP/s counts an FMA as 2 and packed pairs)
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
-# algorithmic lane-ops per row of one exact coordinate update: sign test of
-# r_i x_ij, |x_ij|, two weight accumulations (below / at the current value),
-# one residual FMA
-OPS_PER_ROW_UPDATE = 5
+# algorithmic lane-ops per row of one exact coordinate update (the low end
+# of 12-30): classification pass |x|, sign test, zero test, two weight
+# selects and sums; moving pass |r|, reciprocal, product, side test, running
+# minimum; residual FMA
+OPS_PER_ROW_UPDATE = 12
 METRIC = "LAD-LASSO solves/sec at 1e-5 rel objective vs plain kernel; achieved HBM GB/s"
+
+# device sources whose hash the committed byte-counter summaries record
+KERNEL_SOURCES = ["ladl_solve_wave.hip", "ladl_wave.hpp", "ladl_common.hpp", "ladl_kernels.hpp"]
 
 
 def make_workload(cfg: str):
     from paper_2510_15649_amd import workloads as W
     return {"c1": lambda: W.config1(), "c1path": lambda: W.config1(as_path=True), "c2": lambda: W.config2(),
             "c3": lambda: W.config3(), "c4": lambda: W.config4(),
-            "c4s": lambda: W.config4(problems=range(C4_SAMPLE))}[cfg]()
-
-
-# problems of the 65536-problem ragged path workload timed by default (the
-# generator draws each problem independently, so the first 4096 are a
-# uniform sample of the full draw)
-C4_SAMPLE = 4096
-
-
-# device sources whose hash the committed byte-counter summaries record
-KERNEL_SOURCES = ["ladl_solve_wave.hip", "ladl_wave.hpp", "ladl_common.hpp", "ladl_kernels.hpp"]
+            "c4s": lambda: W.config4(problems=range(4096))}[cfg]()
 
 
 def kernel_source_sha():
@@ -75,9 +78,46 @@ def recorded_traffic(summary, key):
     return int(vals[key])
 
 
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "os_cpu_count": os.cpu_count(), "usable_cpus": usable}
+
+
 def log(msg):
     """Progress to stderr (the JSON line is the only stdout output)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def rows_per_lane(n):
+    r, R = (n + 63) // 64, 1
+    while R < r:
+        R <<= 1
+    return R
+
+
+def median_ms(torch, fn, reps, stream):
+    """Median of `reps` launches, each bracketed by HIP events on `stream`."""
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts)), ts
 
 
 def backward_bytes(w, out_np, step):
@@ -87,15 +127,16 @@ def backward_bytes(w, out_np, step):
     wr = 4 * (w.X.size + w.y.size)
     L = w.path_len
     act = out_np["active"].reshape(-1, L)[:, step]
-    ns = np.array([bin(int(a)).count("1") for a in act], dtype=np.int64)
+    ns = np.array([bin(int(a) & 0xFFFFFFFF).count("1") for a in act], dtype=np.int64)
     ps = w.p[w.problem].astype(np.int64)
     rd = int(np.sum(4 * (2 * ps + 32 + 1 + ns * ns)))
     return int(wr + rd)
 
 
-def measure(L, torch, w, steps, warmup, parity_sample, autotune=False, **opts):
-    """Times `steps` solves of workload w (after `warmup`), checks a seeded
-    parity sample against the oracle.  Returns a dict."""
+def measure(L, torch, w, steps, warmup, parity_solves, autotune=False, **opts):
+    """Times `steps` solves of workload w (after `warmup`) with HIP events on
+    the caller's stream, and each bucket's kernel with HIP events on its own
+    stream; checks the listed solves against the oracle.  Returns a dict."""
     from parity import compare, oracle_ref
     log(f"{w.name}: {w.num_solves * w.path_len} solves, options {opts}")
     dev = torch.device("cuda:0")
@@ -108,6 +149,7 @@ def measure(L, torch, w, steps, warmup, parity_sample, autotune=False, **opts):
     for _ in range(warmup):
         plan.solve(d["X"], d["y"], d["lam"], out=out, stream=stream)
     torch.cuda.synchronize()
+    plan.profile(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(steps):
@@ -115,21 +157,62 @@ def measure(L, torch, w, steps, warmup, parity_sample, autotune=False, **opts):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
-    log(f"{w.name}: {ms:.3f} ms per step; checking {min(parity_sample, w.num_solves)} solves against the oracle")
+    prof = plan.profile_read()
+    plan.profile(False)
+    buckets = plan.buckets()
     n_out = w.num_solves * w.path_len
     g = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
     it = g["iters"].reshape(-1, 4)
-    ns_out = np.repeat(np.diff(w.row_off)[w.problem], w.path_len)
-    row_updates = float(np.sum(it[:, 1].astype(np.float64) * ns_out))
-    rng = np.random.default_rng(2024)
-    sample = np.sort(rng.choice(w.num_solves, size=min(parity_sample, w.num_solves), replace=False))
+    n_solve = np.diff(w.row_off)[w.problem]
+    ns_out = np.repeat(n_solve, w.path_len)
+    upd_rows = it[:, 1].astype(np.float64) * ns_out
+    R_out = np.repeat(np.array([rows_per_lane(int(n)) for n in n_solve]), w.path_len)
+    per_bucket = []
+    for (R, nmax, pmax, count), (bms, launches) in zip(buckets, prof):
+        per_bucket.append({"R": R, "n_max": nmax, "p_max": pmax, "solves": count, "launches": launches,
+                           "ms_per_launch": bms / max(launches, 1),
+                           "row_updates": float(np.sum(upd_rows[R_out == R]))})
+    log(f"{w.name}: {ms:.3f} ms per step; buckets " +
+        ", ".join(f"R={b['R']}: {b['ms_per_launch']:.2f} ms" for b in per_bucket))
+    sample = np.asarray(parity_solves)
+    log(f"{w.name}: checking {len(sample)} solves ({len(sample) * w.path_len} outputs) against the oracle")
     fails, pst = compare(w, g, oracle_ref(w, solves=sample), solves=sample)
+    log(f"{w.name}: parity {'ok' if not fails else 'FAILED'} {pst}")
     status = {L.STATUS_NAMES[s]: int(c) for s, c in zip(*np.unique(g["status"], return_counts=True))}
-    return dict(plan=plan, d=d, ms=ms, solves_per_s=n_out / (ms / 1e3), n_out=n_out, row_updates=row_updates,
-                parity_ok=not fails, parity=pst, fails=fails, status=status,
+    every_ok = bool(np.all(np.isfinite(g["obj"])) and np.all(g["obj"] >= 0))
+    return dict(plan=plan, d=d, out=out, g=g, ms=ms, solves_per_s=n_out / (ms / 1e3), n_out=n_out,
+                row_updates=float(upd_rows.sum()), buckets=per_bucket, parity_ok=not fails and every_ok,
+                parity=pst, fails=fails, status=status,
                 iters_mean={"sweeps": float(it[:, 0].mean()), "updates": float(it[:, 1].mean()),
                             "probes": float(it[:, 2].mean()), "pivots": float(it[:, 3].mean())},
                 describe=plan.describe())
+
+
+def alu_roofline(m, profile_summary=None, traffic_key=None):
+    """ALU roofline of the bucket kernel that takes the longest: algorithmic
+    lane-ops (OPS_PER_ROW_UPDATE per row of each coordinate update it ran)
+    over its average launch time from HIP events on its own stream."""
+    dom = max(m["buckets"], key=lambda b: b["ms_per_launch"])
+    ops = OPS_PER_ROW_UPDATE * dom["row_updates"]
+    achieved = ops / (dom["ms_per_launch"] / 1e3)
+    traffic = recorded_traffic(profile_summary, traffic_key) if profile_summary else None
+    return {"bound": "alu", "kernel": f"k_wave bucket R={dom['R']} (n<={dom['n_max']}, p<={dom['p_max']})",
+            "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "Tlane-op/s",
+            "frac": achieved / PEAK_VALU_LANE_OPS, "traffic": traffic, "ms_per_launch": dom["ms_per_launch"],
+            "work_per_launch_lane_ops": ops, "row_updates": dom["row_updates"],
+            "ops_per_row_update": OPS_PER_ROW_UPDATE}
+
+
+def c4_parity_solves(w, n_uniform=48, n_big=16, seed=2024):
+    """Problems of the ragged batch checked against the oracle along their
+    whole path: a uniform draw plus a draw from those with n > 1024 and
+    p > 24 (the largest bucket)."""
+    rng = np.random.default_rng(seed)
+    ns = np.diff(w.row_off)
+    big = np.flatnonzero((ns > 1024) & (w.p > 24))
+    ids = np.union1d(rng.choice(w.num_solves, size=min(n_uniform, w.num_solves), replace=False),
+                     rng.choice(big, size=min(n_big, len(big)), replace=False) if len(big) else [])
+    return ids.astype(np.int64)
 
 
 def path_graph_and_backward(L, torch, w, s, reps=5):
@@ -149,6 +232,7 @@ def path_graph_and_backward(L, torch, w, s, reps=5):
     torch.cuda.synchronize()
     graph_ms = e0.elapsed_time(e1)
     log(f"{w.name}: path as a HIP graph {graph_ms:.3f} ms")
+    same = all(torch.equal(out[k], s["out"][k]) for k in ("b", "obj", "status", "zero_rows"))
     step = w.path_len - 1
     g = d["grad_b"]
     gy = torch.empty(d["y"].numel(), dtype=torch.float32, device=d["X"].device)
@@ -165,15 +249,65 @@ def path_graph_and_backward(L, torch, w, s, reps=5):
     onp = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
     nbytes = backward_bytes(w, onp, step)
     gbs = nbytes / (bms / 1e3) / 1e9
-    return graph_ms, {"workload": w.name, "kernel": "k_backward", "ms_per_launch": bms, "bound": "hbm",
-                      "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                      "traffic": None, "algorithmic_bytes": nbytes}
+    return graph_ms, same, {"workload": w.name, "kernel": "k_bw_vertex + k_bw_scatter", "ms_per_launch": bms,
+                            "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                            "frac": gbs / PEAK_HBM_GBS, "traffic": None, "algorithmic_bytes": nbytes}
+
+
+def cpu_baseline(L, w, seed=99, target_s=8.0):
+    """The FP64 oracle, with the library's default schedule and tolerances,
+    timed on the host cores on a uniform sample of solves (grown until the
+    run takes target_s), and on one thread on a quarter of that sample."""
+    import oracle as O
+    info = cpu_info()
+    threads = max(1, min(info["usable_cpus"], 16))
+    d_opt = L.default_options()
+    opts = dict(max_rounds=int(d_opt.max_rounds), tol_f=float(d_opt.tol_f), tol_s=float(d_opt.tol_s),
+                max_sweeps=int(d_opt.max_sweeps), max_ternary=int(d_opt.max_ternary),
+                chop_range=float(d_opt.chop_range))
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(w.num_solves)
+    k = min(w.num_solves, max(threads, 8))
+    while True:
+        solves = np.sort(perm[:k])
+        r = O.solve_batch(w, nthreads=threads, solves=solves, **opts)
+        if r["seconds"] >= target_s or k == w.num_solves:
+            break
+        k = min(w.num_solves, k * 2)
+    res = {"value": k * w.path_len / r["seconds"], "unit": "solves/s", "cores": threads, "kind": "oracle",
+           "sample": f"{k} of {w.num_solves} solves x {w.path_len} path steps (uniform, seeded) of {w.name}; "
+                     f"FP64 C oracle with the library's default schedule; {r['seconds']:.1f} s on {threads} "
+                     f"threads", "host": info}
+    k1 = max(1, k // 4)
+    r1 = O.solve_batch(w, nthreads=1, solves=solves[:k1], **opts)
+    res["one_thread"] = {"value": k1 * w.path_len / r1["seconds"], "unit": "solves/s",
+                         "sample": f"{k1} of the sampled solves; {r1['seconds']:.1f} s on 1 thread"}
+    return res
+
+
+def plain_comparison(L, torch, m, w, reps=10, parity=128):
+    """The plain one-thread-per-solve kernel on the workload `m` measured:
+    median of `reps` launches, parity on a sample."""
+    from parity import compare, oracle_ref
+    plan, d = m["plan"], m["d"]
+    stream = torch.cuda.current_stream()
+    out_p = plan.alloc_outputs(d["X"].device, iters=False)
+    fn = lambda: plan.solve_plain(d["X"], d["y"], d["lam"], out=out_p, stream=stream)
+    fn()
+    torch.cuda.synchronize()
+    pms, ts = median_ms(torch, fn, reps, stream)
+    gp = {k: v.cpu().numpy() for k, v in out_p.items() if v is not None}
+    rng = np.random.default_rng(2024)
+    sample = np.sort(rng.choice(w.num_solves, size=min(parity, w.num_solves), replace=False))
+    pf, _ = compare(w, gp, oracle_ref(w, solves=sample), solves=sample)
+    return {"value": m["n_out"] / (pms / 1e3), "unit": "solves/s", "ms_per_step": pms, "launches": reps,
+            "ms_min_max": [float(min(ts)), float(max(ts))], "parity_ok": not pf}
 
 
 def measure_cv(L, torch, folds=5, steps=3, sample=4):
-    """K-fold cross-validation of the 512 c1 problems along their 16-lambda
-    path (the training solves run on the wave kernels); parity of the fold
-    errors on a few problems against the oracle's cross-validation."""
+    """K-fold cross-validation of the 512 problems of n=200, p=8 along their
+    16-lambda path (the training solves run on the wave kernels); parity of
+    the fold errors on a few problems against the oracle's cross-validation."""
     import oracle as O
     from paper_2510_15649_amd import workloads as W
     w = W.config1(as_path=True)
@@ -255,24 +389,34 @@ def measure_brute(L, torch, steps=3, sample=16):
             "oracle_1_thread_solves_per_s": cpu_rate}
 
 
+def secondary_entry(w, s, mr, fl):
+    return {"workload": w.name, "max_rounds": mr, "golden": bool(fl), "solves_per_s": s["solves_per_s"],
+            "ms_per_step": s["ms"], "parity_ok": s["parity_ok"], "max_rel_f": s["parity"]["max_rel_f"],
+            "strict_of_unique": [s["parity"]["strict"], s["parity"]["unique"]],
+            "iters_mean": s["iters_mean"], "status": s["status"], "buckets": s["buckets"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c1")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c4")
     ap.add_argument("--max-rounds", type=int, default=1)
     ap.add_argument("--golden", action="store_true")
     ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--team", type=int, default=0,
+                    help="waves per solve for n > 1024 (0: the library's choice; 1, 2 or 4)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--parity-sample", type=int, default=256)
+    ap.add_argument("--parity-sample", type=int, default=48,
+                    help="solves of the headline workload checked against the oracle (plus 16 of the largest "
+                         "problems on the ragged batch)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a known-size reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solves are independent, so a "
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): every solve is independent, so a "
               f"multi-GPU run is this kernel on each GPU's share of the queue", file=sys.stderr)
         sys.exit(2)
 
@@ -292,87 +436,59 @@ def main():
     log(f"generating workload {args.config}")
     w = make_workload(args.config)
     flags = L.FLAG_GOLDEN if args.golden else 0
-    m = measure(L, torch, w, args.steps, args.warmup, args.parity_sample, args.autotune,
-                max_rounds=args.max_rounds, flags=flags)
+    if args.config in ("c4", "c4s"):
+        psolves = c4_parity_solves(w, n_uniform=args.parity_sample)
+    else:
+        rng = np.random.default_rng(2024)
+        psolves = np.sort(rng.choice(w.num_solves, size=min(args.parity_sample, w.num_solves), replace=False))
+    m = measure(L, torch, w, args.steps, args.warmup, psolves, args.autotune, max_rounds=args.max_rounds,
+                flags=flags, team=args.team)
     ms = m["ms"]
-    main_graph_ms, main_backward = None, None
-    if w.path_len > 1 and w.grad_b is not None:
-        main_graph_ms, main_backward = path_graph_and_backward(L, torch, w, m)
-    lane_ops = OPS_PER_ROW_UPDATE * m["row_updates"]
-    achieved_ops = lane_ops / (ms / 1e3)
+    default_run = args.max_rounds == 1 and not args.golden and not args.autotune and args.team == 0
+    summary = {"c4": "k_wave_c4_full_hbm_bytes.md", "c2": "k_wave_c2_hbm_bytes.md",
+               "c1": "k_wave_c1_hbm_bytes.md"}.get(args.config) if default_run else None
+    roof = alu_roofline(m, summary, "traffic_bytes_per_launch")
     alg_bytes = w.algorithmic_bytes()
     hbm_gbs = alg_bytes / (ms / 1e3) / 1e9
-    default_c1 = args.config == "c1" and args.max_rounds == 1 and not args.golden and not args.autotune
-    traffic = recorded_traffic("k_wave_c1_hbm_bytes.md", "traffic_bytes_per_launch") if default_c1 else None
-
-    plain = None
-    if not args.no_plain:
-        log("plain one-thread-per-solve kernel")
-        from parity import compare, oracle_ref
-        plan, d = m["plan"], m["d"]
-        stream = torch.cuda.current_stream()
-        out_p = plan.alloc_outputs(d["X"].device, iters=False)
-        plan.solve_plain(d["X"], d["y"], d["lam"], out=out_p, stream=stream)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        plan.solve_plain(d["X"], d["y"], d["lam"], out=out_p, stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        pms = e0.elapsed_time(e1)
-        gp = {k: v.cpu().numpy() for k, v in out_p.items() if v is not None}
-        rng = np.random.default_rng(2024)
-        sample = np.sort(rng.choice(w.num_solves, size=min(args.parity_sample, w.num_solves), replace=False))
-        pf, _ = compare(w, gp, oracle_ref(w, solves=sample), solves=sample)
-        plain = {"value": m["n_out"] / (pms / 1e3), "ms_per_step": pms, "parity_ok": not pf}
+    graph_ms = graph_same = backward = None
+    if w.path_len > 1 and w.grad_b is not None:
+        graph_ms, graph_same, backward = path_graph_and_backward(L, torch, w, m)
+        if args.config == "c4" and default_run:
+            backward["traffic"] = recorded_traffic("k_bw_c4_full_hbm_bytes.md", "backward_traffic_bytes_per_launch")
 
     cpu = None
     if not args.no_cpu:
         log("oracle on the host cores")
-        import oracle as O
-        threads = min(os.cpu_count() or 1, 16)
-        rng = np.random.default_rng(99)
-        d_opt = L.default_options()
-        opts = dict(max_rounds=args.max_rounds, tol_f=float(d_opt.tol_f), tol_s=float(d_opt.tol_s),
-                    max_sweeps=int(d_opt.max_sweeps), max_ternary=int(d_opt.max_ternary),
-                    chop_range=float(d_opt.chop_range))
-        k = min(w.num_solves, 64)
-        while True:
-            solves = np.sort(rng.choice(w.num_solves, size=k, replace=False))
-            r = O.solve_batch(w, nthreads=threads, solves=solves, **opts)
-            if r["seconds"] >= 5.0 or k == w.num_solves:
-                break
-            k = min(w.num_solves, k * 4)
-        cpu = {"value": k * w.path_len / r["seconds"], "unit": "solves/s", "cores": threads, "kind": "oracle",
-               "sample": f"{k} of {w.num_solves} solves (uniform, seeded); FP64 C oracle with the same schedule "
-                         f"(max_rounds={args.max_rounds}); {r['seconds']:.1f} s on {threads} threads"}
-        # the same oracle on one host thread, on the first quarter of that sample
-        k1 = max(1, k // 4)
-        r1 = O.solve_batch(w, nthreads=1, solves=solves[:k1], **opts)
-        cpu["one_thread"] = {"value": k1 * w.path_len / r1["seconds"], "unit": "solves/s",
-                             "sample": f"{k1} of the sampled solves; {r1['seconds']:.1f} s on 1 thread"}
+        cpu = cpu_baseline(L, w)
+        log(f"oracle: {cpu['value']:.1f} solves/s on {cpu['cores']} threads")
 
     secondary = []
-    backward = main_backward
+    plain = None
     if not args.no_secondary:
-        for cfg, mr, fl in [("c1", 0, 0), ("c1", 1, L.FLAG_GOLDEN), ("c2", 1, 0), ("c2", 0, 0), ("c3", 1, 0),
-                            ("c4s", 1, 0)]:
+        for cfg, mr, fl in [("c1", 1, 0), ("c1", 0, 0), ("c1", 1, L.FLAG_GOLDEN), ("c2", 1, 0), ("c2", 0, 0),
+                            ("c3", 1, 0)]:
             if cfg == args.config and mr == args.max_rounds and fl == flags:
                 continue
             log(f"generating workload {cfg}")
             ws = make_workload(cfg)
-            big = cfg == "c4s"
-            s = measure(L, torch, ws, 2 if big else 3, 1, 8 if big else 128, args.autotune, max_rounds=mr, flags=fl)
-            entry = {"workload": ws.name, "max_rounds": mr, "golden": bool(fl), "solves_per_s": s["solves_per_s"],
-                     "ms_per_step": s["ms"], "parity_ok": s["parity_ok"], "max_rel_f": s["parity"]["max_rel_f"],
-                     "iters_mean": s["iters_mean"], "status": s["status"]}
-            if big:
-                entry["graph_ms_per_step"], bw = path_graph_and_backward(L, torch, ws, s)
-                bw["traffic"] = recorded_traffic("c4_sample_kernel_stats.md", "backward_traffic_bytes_per_launch")
-                backward = backward or bw
-            elif cfg == "c3":
-                # the differentiation workload: its backward (dL/dy, dL/dX of all 1024 problems)
-                _, entry["backward"] = path_graph_and_backward(L, torch, ws, s)
+            rng = np.random.default_rng(2024)
+            samp = np.sort(rng.choice(ws.num_solves, size=min(128, ws.num_solves), replace=False))
+            s = measure(L, torch, ws, 3, 1, samp, args.autotune, max_rounds=mr, flags=fl)
+            entry = secondary_entry(ws, s, mr, fl)
+            if cfg == "c1" and mr == 1 and fl == 0:
+                log("plain one-thread-per-solve kernel, median of 10 launches")
+                plain = plain_comparison(L, torch, s, ws)
+                entry["plain_kernel"] = plain
+                entry["vs_plain"] = s["solves_per_s"] / plain["value"]
+                entry["roofline"] = alu_roofline(s, "k_wave_c1_hbm_bytes.md", "traffic_bytes_per_launch")
+            if cfg == "c2" and mr == 1:
+                gbs = ws.algorithmic_bytes() / (s["ms"] / 1e3) / 1e9
+                entry["hbm"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                "frac": gbs / PEAK_HBM_GBS, "algorithmic_bytes": ws.algorithmic_bytes(),
+                                "traffic": recorded_traffic("k_wave_c2_hbm_bytes.md", "traffic_bytes_per_launch")}
+                entry["roofline"] = alu_roofline(s)
+            if cfg == "c3":
+                entry["backward"] = backward_c3(L, torch, ws, s)
             secondary.append(entry)
         secondary.append(measure_cv(L, torch))
         secondary.append(measure_brute(L, torch))
@@ -386,25 +502,43 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic (seeded generator, no dataset)",
         "config": {"workload": w.name, "solves_per_step": m["n_out"], "max_rounds": args.max_rounds,
-                   "golden": bool(args.golden), "autotune": bool(args.autotune),
-                   "parallelism": "1 GPU, one wavefront per solve", "path_len": w.path_len,
-                   "graph_ms_per_step": main_graph_ms},
-        "roofline": {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
-                     "unit": "Tlane-op/s", "frac": achieved_ops / PEAK_VALU_LANE_OPS, "traffic": traffic,
-                     "work_per_launch_lane_ops": lane_ops, "row_updates": m["row_updates"]},
+                   "golden": bool(args.golden), "autotune": bool(args.autotune), "team": args.team,
+                   "parallelism": "1 GPU, one wavefront per solve, buckets side by side",
+                   "path_len": w.path_len, "graph_ms_per_step": graph_ms, "graph_equals_in_kernel": graph_same},
+        "roofline": roof,
         "hbm": {"achieved_GBs": hbm_gbs, "peak_GBs": PEAK_HBM_GBS, "frac": hbm_gbs / PEAK_HBM_GBS,
                 "algorithmic_bytes": alg_bytes},
         "cpu_baseline": cpu,
         "plain_kernel": plain,
-        "vs_plain": (m["solves_per_s"] / plain["value"]) if plain else None,
-        "parity": {"ok": m["parity_ok"], "sample": m["parity"]["outputs"], **m["parity"],
+        "vs_plain": None,
+        "parity": {"ok": m["parity_ok"], "sample_solves": int(len(psolves)), **m["parity"],
                    "first_failures": [str(f) for f in m["fails"][:3]]},
         "status": m["status"],
         "iters_mean": m["iters_mean"],
+        "buckets": m["buckets"],
         "secondary": secondary,
         "roofline_backward": backward,
     }
     print(json.dumps(line), flush=True)
+
+
+def backward_c3(L, torch, w, s, reps=5):
+    """Backward of a single-step workload (the differentiation workload)."""
+    plan, d = s["plan"], s["d"]
+    stream = torch.cuda.current_stream()
+    g = d["grad_b"]
+    gy = torch.empty(d["y"].numel(), dtype=torch.float32, device=d["X"].device)
+    gX = torch.empty_like(d["X"])
+    plan.backward(d["X"], s["out"], g, grad_y=gy, grad_X=gX, stream=stream)
+    torch.cuda.synchronize()
+    bms, _ = median_ms(torch, lambda: plan.backward(d["X"], s["out"], g, grad_y=gy, grad_X=gX, stream=stream),
+                       reps, stream)
+    nbytes = backward_bytes(w, s["g"], 0)
+    gbs = nbytes / (bms / 1e3) / 1e9
+    zero = int(np.sum(~np.isin(s["g"]["status"], [L.CERTIFIED, L.NONUNIQUE])))
+    return {"workload": w.name, "kernel": "k_bw_vertex + k_bw_scatter", "ms_per_launch": bms, "bound": "hbm",
+            "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+            "algorithmic_bytes": nbytes, "solves_without_gradient": zero}
 
 
 if __name__ == "__main__":

@@ -51,11 +51,16 @@ enum {
 
 /* per-solve status written to `status` */
 enum {
-    LADL_CERTIFIED = 0,    /* optimality certificate holds with margin: the
-                              minimiser, Z and S are unique                  */
-    LADL_NONUNIQUE = 1,    /* certificate holds at a degenerate or nearly
-                              degenerate vertex: f is optimal, b may not be
-                              the only minimiser                             */
+    LADL_CERTIFIED = 0,    /* optimality certificate holds with margins the
+                              fp32 computation resolves: the minimiser, Z
+                              and S are unique.  Margins: 1 - |u_i| > 2e-5 on
+                              Z; (lambda - |c_j|) / (lambda + sum_{i in Z}
+                              |x_ij|) > 2e-5 off S; |r_i| / (|y_i| + sum_j
+                              |x_ij b_j|) > 1e-6 off Z                       */
+    LADL_NONUNIQUE = 1,    /* certificate holds, but a margin is below those
+                              thresholds (a degenerate or nearly degenerate
+                              vertex): f is optimal, b may not be the only
+                              minimiser                                      */
     LADL_MAXITER = 2,      /* finisher pivot cap reached before certifying   */
     LADL_NONFINITE = 3,    /* NaN or Inf in this problem's X or y            */
     LADL_BADLAMBDA = 4,    /* lambda < 0 or NaN                              */
@@ -106,6 +111,12 @@ typedef struct {
                             b_k, as a fraction of max(1, |b_k|); the range
                             is doubled while an end is lower than the
                             centre (Section 3.6)               (default 1/32) */
+    int32_t team;        /* waves per solve for problems of n > 1024: 0 the
+                            library's choice (ladl_autotune may change it),
+                            1 one wavefront, 2 or 4 a team of that many
+                            wavefronts of one workgroup, the rows split
+                            between them; smaller problems always take one
+                            wavefront                          (default 0)    */
 } ladl_options;
 
 /*
@@ -195,8 +206,12 @@ int ladl_solve_plain_f32(ladl_plan_t plan, const float *X, const float *y, const
  * Gradient of a loss L through the solution at path step `step` (usually
  * path_len - 1), using b_S = X_{Z,S}^{-1} y_Z at the optimal vertex:
  *   w = X_{Z,S}^{-T} g_S,  dL/dy_Z = w,  dL/dX_{Z,S} = -w b_S^T,
- * every other entry 0 (the vertex form of Section 3.2).  Solves whose
- * status is not LADL_CERTIFIED get zero gradients.
+ * every other entry 0 (the vertex form of Section 3.2).  Every certified
+ * output (LADL_CERTIFIED or LADL_NONUNIQUE) with |Z| = |S| > 0 and a
+ * non-singular X_{Z,S} gets this gradient; at LADL_NONUNIQUE it is the
+ * derivative of the returned vertex (one of the one-sided derivatives of
+ * the solution map).  Outputs with b = 0, or without a certificate, get
+ * zero gradients (b = 0 with a certificate is locally constant).
  *   b, zero_rows, status   device, the forward outputs (all steps)
  *   grad_b     device, packed like one path step of b
  *   grad_y     device, packed like y (output; all y_len floats written,
@@ -234,6 +249,24 @@ int ladl_graph_destroy(ladl_graph_t graph);
  */
 int ladl_autotune(ladl_plan_t plan, const float *X, const float *y, const float *lambda, float *b,
                   float *obj, uint32_t *active, int32_t *zero_rows, int32_t *status, void *stream);
+
+/*
+ * Kernel timing per bucket, for measuring the solve kernels on their own
+ * streams (the buckets of a plan run side by side on streams forked from
+ * the caller's).  ladl_plan_profile(plan, 1) drops earlier records and
+ * starts recording: every later ladl_solve_f32 on the plan records a HIP
+ * event pair on each bucket's stream around that bucket's kernel (graph
+ * launches are not recorded); ladl_plan_profile(plan, 0) stops and drops
+ * them.  ladl_plan_profile_read waits for the recorded events and writes,
+ * per bucket in the order ladl_plan_describe lists them, the summed kernel
+ * time in ms (host float [max_buckets]) and the number of launches (host
+ * int32 [max_buckets]); *num_buckets receives the bucket count
+ * (LADL_EINVAL if max_buckets is smaller).  Events are created per launch
+ * while recording, so leave it off outside measurements.
+ */
+int ladl_plan_profile(ladl_plan_t plan, int32_t enable);
+int ladl_plan_profile_read(ladl_plan_t plan, float *ms, int32_t *launches, int32_t max_buckets,
+                           int32_t *num_buckets);
 
 /* Describe the plan's buckets and schedules as text (host buffer). */
 int ladl_plan_describe(ladl_plan_t plan, char *buf, int64_t buf_len);

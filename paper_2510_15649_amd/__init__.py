@@ -29,14 +29,15 @@ EXPORTED = ["ladl_create", "ladl_destroy", "ladl_default_options", "ladl_plan_cr
             "ladl_plan_b_len", "ladl_solve_f32", "ladl_solve_plain_f32", "ladl_backward_f32",
             "ladl_graph_create", "ladl_graph_launch", "ladl_graph_destroy", "ladl_autotune",
             "ladl_plan_describe", "ladl_error_string", "ladl_last_error_detail", "ladl_cv_create",
-            "ladl_cv_destroy", "ladl_cv_run", "ladl_brute_force_f32", "ladl_selection_frequency"]
+            "ladl_cv_destroy", "ladl_cv_run", "ladl_brute_force_f32", "ladl_selection_frequency",
+            "ladl_plan_profile", "ladl_plan_profile_read"]
 
 
 class Options(C.Structure):
     _fields_ = [("tol_f", C.c_float), ("tol_s", C.c_float), ("lambda_min", C.c_float),
                 ("max_sweeps", C.c_int32), ("max_ternary", C.c_int32), ("max_rounds", C.c_int32),
                 ("max_pivots", C.c_int32), ("flags", C.c_int32), ("schedule", C.c_int32),
-                ("chop_range", C.c_float)]
+                ("chop_range", C.c_float), ("team", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -98,6 +99,8 @@ def lib() -> C.CDLL:
     L.ladl_cv_create.argtypes = [vp, C.POINTER(CVLayout), C.POINTER(Options), C.POINTER(vp)]
     L.ladl_cv_destroy.argtypes = [vp]
     L.ladl_cv_run.argtypes = [vp] + [vp] * 7 + [vp]
+    L.ladl_plan_profile.argtypes = [vp, i32]
+    L.ladl_plan_profile_read.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(i32), i32, C.POINTER(i32)]
     L.ladl_error_string.argtypes = [C.c_int]
     L.ladl_error_string.restype = C.c_char_p
     L.ladl_last_error_detail.argtypes = []
@@ -105,7 +108,8 @@ def lib() -> C.CDLL:
     for name in ["ladl_create", "ladl_destroy", "ladl_plan_create", "ladl_plan_destroy", "ladl_solve_f32",
                  "ladl_solve_plain_f32", "ladl_backward_f32", "ladl_graph_create", "ladl_graph_launch",
                  "ladl_graph_destroy", "ladl_autotune", "ladl_plan_describe", "ladl_cv_create", "ladl_cv_destroy",
-                 "ladl_cv_run", "ladl_brute_force_f32", "ladl_selection_frequency"]:
+                 "ladl_cv_run", "ladl_brute_force_f32", "ladl_selection_frequency",
+                 "ladl_plan_profile", "ladl_plan_profile_read"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -159,6 +163,27 @@ def _ptr(t) -> Optional[int]:
     if t is None:
         return None
     return C.c_void_p(t.data_ptr())
+
+
+_DTYPES = {"f32": "torch.float32", "i32": "torch.int32", "i64": "torch.int64"}
+
+
+def _check(t, name: str, kind: str, min_numel: int, optional: bool = False):
+    """The C ABI cannot see device buffer sizes or element types: a tensor
+    handed to it must be a contiguous device tensor of the expected dtype
+    holding at least `min_numel` elements, else ValueError."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name} is required")
+    if str(t.dtype) != _DTYPES[kind]:
+        raise ValueError(f"{name} must be {_DTYPES[kind]} (got {t.dtype})")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor (got {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < min_numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, the plan needs {min_numel}")
 
 
 def _stream(stream):
@@ -216,6 +241,7 @@ class Plan:
         check(lib().ladl_plan_create(self.handle.ptr, C.byref(lay), C.byref(self.options), C.byref(h)))
         self._plan = h
         self.num_problems, self.num_solves, self.path_len = P, S, int(path_len)
+        self.x_len, self.y_len = int(x_len), int(y_len)
         self.b_len = int(lib().ladl_plan_b_len(h))
         prob = np.arange(S, dtype=np.int32) if self._problem is None else self._problem
         self.p_per_solve = self.p_per_problem[prob]
@@ -248,7 +274,25 @@ class Plan:
                     status=torch.empty(n_out, dtype=torch.int32, device=device),
                     iters=torch.empty(n_out * 4, dtype=torch.int32, device=device) if iters else None)
 
+    def _check_inputs(self, X, y, lam, b_init=None):
+        n_out = self.num_solves * self.path_len
+        _check(X, "X", "f32", self.x_len)
+        _check(y, "y", "f32", self.y_len)
+        _check(lam, "lam", "f32", n_out)
+        _check(b_init, "b_init", "f32", self.b_len // self.path_len, optional=True)
+
+    def _check_outputs(self, out):
+        n_out = self.num_solves * self.path_len
+        _check(out.get("b"), "b", "f32", self.b_len)
+        _check(out.get("obj"), "obj", "f32", n_out)
+        _check(out.get("active"), "active", "i32", n_out)
+        _check(out.get("zero_rows"), "zero_rows", "i32", ZPAD * n_out)
+        _check(out.get("status"), "status", "i32", n_out)
+        _check(out.get("iters"), "iters", "i32", 4 * n_out, optional=True)
+
     def _call(self, fn, X, y, lam, b_init, out, stream):
+        self._check_inputs(X, y, lam, b_init)
+        self._check_outputs(out)
         check(fn(self._plan, _ptr(X), _ptr(y), _ptr(lam), _ptr(b_init), _ptr(out["b"]), _ptr(out["obj"]),
                  _ptr(out["active"]), _ptr(out["zero_rows"]), _ptr(out["status"]), _ptr(out.get("iters")),
                  _stream(stream)))
@@ -271,6 +315,10 @@ class Plan:
         group: device int32 [num_solves] or None.  Returns device tensors
         freq [G, L, 32], counts [G, L, 33] and bad_group [1]."""
         import torch
+        n_out = self.num_solves * self.path_len
+        _check(out.get("active"), "active", "i32", n_out)
+        _check(out.get("status"), "status", "i32", n_out)
+        _check(group, "group", "i32", self.num_solves, optional=True)
         dev = out["active"].device
         G, Lp = int(num_groups), self.path_len
         res = dict(freq=torch.empty(G * Lp * 32, dtype=torch.float32, device=dev),
@@ -287,6 +335,7 @@ class Plan:
         """Exact solve by vertex enumeration on the device (small problems:
         p <= 8, n + p <= 64).  Returns device tensors b, obj, vertices."""
         import torch
+        self._check_inputs(X, y, lam)
         n_out = self.num_solves * self.path_len
         out = dict(b=torch.empty(self.b_len, dtype=torch.float32, device=X.device),
                    obj=torch.empty(n_out, dtype=torch.float32, device=X.device),
@@ -301,15 +350,50 @@ class Plan:
         grad_y = grad_y if grad_y is not None else torch.empty(int(self._row_off[-1]), dtype=torch.float32,
                                                                  device=X.device)
         grad_X = grad_X if grad_X is not None else torch.empty_like(X)
+        n_out = self.num_solves * self.path_len
+        _check(X, "X", "f32", self.x_len)
+        _check(out.get("b"), "b", "f32", self.b_len)
+        _check(out.get("zero_rows"), "zero_rows", "i32", ZPAD * n_out)
+        _check(out.get("status"), "status", "i32", n_out)
+        _check(grad_b, "grad_b", "f32", self.b_len // self.path_len)
+        _check(grad_y, "grad_y", "f32", self.y_len)
+        _check(grad_X, "grad_X", "f32", self.x_len)
         check(lib().ladl_backward_f32(self._plan, _ptr(X), _ptr(out["b"]), _ptr(out["zero_rows"]),
                                       _ptr(out["status"]), int(step), _ptr(grad_b), _ptr(grad_y),
                                       _ptr(grad_X), _stream(stream)))
         return grad_y, grad_X
 
+    def profile(self, enable: bool = True):
+        """Start (or stop) recording each bucket's kernel time with HIP events
+        on the bucket's own stream."""
+        check(lib().ladl_plan_profile(self._plan, 1 if enable else 0))
+
+    def profile_read(self):
+        """Per bucket (in describe() order): (summed kernel ms, launches)
+        since profiling started; waits for the recorded events."""
+        nb = C.c_int32(0)
+        ms = (C.c_float * 16)()
+        cnt = (C.c_int32 * 16)()
+        check(lib().ladl_plan_profile_read(self._plan, ms, cnt, 16, C.byref(nb)))
+        return [(float(ms[i]), int(cnt[i])) for i in range(nb.value)]
+
+    def buckets(self):
+        """(R, n_max, pmax, solves) of each bucket, in describe() order."""
+        import re
+        return [tuple(int(v) for v in m.groups()) for m in
+                re.finditer(r"bucket R=(\d+) \(n<=(\d+)\) pmax=(\d+) solves=(\d+)", self.describe())]
+
+    def waves_per_solve(self):
+        """Waves per solve (team size) of each bucket, in describe() order."""
+        import re
+        return [int(v) for v in re.findall(r"waves/solve=(\d+)", self.describe())]
+
     def graph(self, X, y, lam, out, b_init=None) -> "PathGraph":
         return PathGraph(self, X, y, lam, out, b_init)
 
     def autotune(self, X, y, lam, out, stream=None):
+        self._check_inputs(X, y, lam)
+        self._check_outputs(out)
         check(lib().ladl_autotune(self._plan, _ptr(X), _ptr(y), _ptr(lam), _ptr(out["b"]), _ptr(out["obj"]),
                                   _ptr(out["active"]), _ptr(out["zero_rows"]), _ptr(out["status"]),
                                   _stream(stream)))
@@ -325,6 +409,8 @@ class PathGraph:
     """The lambda path captured as a HIP graph of path_len launches."""
 
     def __init__(self, plan: Plan, X, y, lam, out, b_init=None):
+        plan._check_inputs(X, y, lam, b_init)
+        plan._check_outputs(out)
         self.plan = plan
         self._keep = (X, y, lam, out, b_init)
         g = C.c_void_p()
@@ -376,6 +462,7 @@ class CrossValidation:
         check(lib().ladl_cv_create(self.handle.ptr, C.byref(lay), C.byref(self.options), C.byref(h)))
         self._cv = h
         self.num_problems, self.folds, self.path_len = P, int(folds), int(path_len)
+        self.x_len, self.y_len = int(x_len), int(y_len)
 
     @classmethod
     def for_workload(cls, w, folds: int, **kw) -> "CrossValidation":
@@ -388,6 +475,9 @@ class CrossValidation:
         fold_status [P*K*L] (enqueued on `stream`)."""
         import torch
         P, K, L = self.num_problems, self.folds, self.path_len
+        _check(X, "X", "f32", self.x_len)
+        _check(y, "y", "f32", self.y_len)
+        _check(lam, "lam", "f32", P * L)
         out = dict(fold_error=torch.empty(P * K * L, dtype=torch.float32, device=X.device),
                    cv_error=torch.empty(P * L, dtype=torch.float32, device=X.device),
                    best=torch.empty(P, dtype=torch.int32, device=X.device),

@@ -4,8 +4,9 @@ forward: the batched solve (HIP kernels) for the plan's layout.
 backward: the hand-written gradient kernel through the optimal vertex,
 giving dL/dX and dL/dy (lambda gets no gradient: the solution is piecewise
 constant in lambda at a fixed vertex, so its derivative is zero almost
-everywhere).  Solves whose optimum is not certified unique get zero
-gradients.
+everywhere).  Solves without an optimality certificate get zero
+gradients; at a certified but non-unique optimum the gradient is that of
+the returned vertex.
 """
 from __future__ import annotations
 

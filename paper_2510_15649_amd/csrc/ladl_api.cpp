@@ -40,6 +40,7 @@ constexpr int KNOWN_FLAGS = LADL_FLAG_GOLDEN | LADL_FLAG_NO_FINISHER | LADL_FLAG
 constexpr int NMAX_ROWS = 2048;     // rows per problem (32 slots x 64 lanes)
 constexpr size_t LDS_RESIDENT_MAX = 40 * 1024; // larger buckets keep X in the global workspace
 constexpr int DENSE_MIN_ROUNDS = 2;             // solves per wave above which the dense variant is used
+constexpr int TEAM_R32_DEFAULT = 1;             // waves per solve for n > 1024 unless the options say
 
 int rows_per_lane(int n)
 {
@@ -62,6 +63,7 @@ struct Bucket {
     int grid = 0;
     bool xg = false;           // X in the global workspace instead of LDS
     bool dense = false;        // the kernel variant built for 4 waves per SIMD
+    int tw = 1;                // waves per solve (a team for tw > 1)
     int nlds = 0;              // with the workspace: columns of X kept in LDS
     int per_cu = 0;
     int64_t ws_off = 0;        // this bucket's slice of the workspace
@@ -92,6 +94,10 @@ struct ladl_plan_s {
     hipEvent_t ev_fork = nullptr;
     int nmax = 0, pmax = 0;
     bool problems_once = false; // every problem used by exactly one solve
+    // kernel timing: an event pair around each bucket's launch, recorded on
+    // the bucket's stream while profiling is on
+    bool profiling = false;
+    std::vector<std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof;
 };
 
 struct ladl_graph_s {
@@ -101,7 +107,7 @@ struct ladl_graph_s {
 };
 
 static int layout_workspace(ladl_plan_t pl);
-static void set_schedule(ladl_plan_t pl, Bucket &b, bool xg, bool dense = false);
+static void set_schedule(ladl_plan_t pl, Bucket &b, bool xg, bool dense = false, int tw = 1);
 
 // exported functions: C linkage comes from their declarations in ladlasso.h
 
@@ -132,6 +138,7 @@ void ladl_default_options(ladl_options *o)
     o->flags = 0;
     o->schedule = -1;
     o->chop_range = 0.03125f;
+    o->team = 0;
 }
 
 int ladl_create(ladl_handle_t *handle)
@@ -179,11 +186,24 @@ static int check_options(const ladl_options *o)
     if (o->schedule < -1 || o->schedule > 1) return fail(LADL_EINVAL, "unknown schedule %d", o->schedule);
     if (!(o->chop_range > 0.f) || !std::isfinite(o->chop_range))
         return fail(LADL_EINVAL, "chop_range must be finite and > 0");
+    if (o->team != 0 && o->team != 1 && o->team != 2 && o->team != 4)
+        return fail(LADL_EINVAL, "team must be 0, 1, 2 or 4 (got %d)", o->team);
     return LADL_OK;
+}
+
+static void prof_clear(ladl_plan_s *pl)
+{
+    for (auto &v : pl->prof)
+        for (auto &e : v) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    pl->prof.clear();
 }
 
 static void plan_free_device(ladl_plan_s *pl)
 {
+    prof_clear(pl);
     (void)hipFree(pl->d_row_off);
     (void)hipFree(pl->d_x_off);
     (void)hipFree(pl->d_b_off);
@@ -325,16 +345,21 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         for (int s : ids) b.pmax = std::max(b.pmax, (int)pl->p[pl->problem[s]]);
         b.count = (int)ids.size();
         order.insert(order.end(), ids.begin(), ids.end());
-        const bool xg = o.schedule >= 0 || R >= 32 || wave_lds_bytes(R, b.pmax, false, 0) > LDS_RESIDENT_MAX;
-        size_t lds = wave_lds_bytes(R, b.pmax, xg, 0);
+        const bool xg = o.schedule >= 0 || R >= 32 || wave_lds_bytes(R, b.pmax, false, 0, 1) > LDS_RESIDENT_MAX;
+        size_t lds = wave_lds_bytes(R, b.pmax, xg, 0, 1);
         if (lds > h->lds_max)
             return bad(LADL_EUNSUPPORTED, "bucket R=%d p=%d needs %zu bytes of LDS (device limit %zu)", R, b.pmax,
                        lds, h->lds_max);
-        set_schedule(pl, b, xg);
+        // waves per solve: the option, else the static choice (one wave, or
+        // a team for the n > 1024 bucket)
+        const int tw = (o.team > 0 && wave_has_team(R, o.team)) ? o.team
+                                                                 : (o.team == 0 && R >= 32 ? TEAM_R32_DEFAULT : 1);
+        set_schedule(pl, b, xg, false, tw);
         // the dense variant where the bucket holds more than DENSE_MIN_ROUNDS
         // full grids of solves: the extra waves then shorten every round
         // (c1, 8192 solves of n = 200, p = 8: 3.82 instead of 4.0 ms)
-        if (wave_has_dense(R) && (o.schedule == 1 || (o.schedule == -1 && b.count > DENSE_MIN_ROUNDS * b.grid)))
+        if (b.tw == 1 && wave_has_dense(R) &&
+            (o.schedule == 1 || (o.schedule == -1 && b.count > DENSE_MIN_ROUNDS * b.grid)))
             set_schedule(pl, b, true, true);
         pl->buckets.push_back(b);
     }
@@ -458,7 +483,7 @@ static int layout_workspace(ladl_plan_t pl)
     int64_t tot = 0;
     for (Bucket &b : pl->buckets) {
         b.ws_off = tot;
-        if (b.xg) tot += (int64_t)b.grid * (int64_t)wave_ws_floats_host(b.R, b.pmax, b.nlds);
+        if (b.xg) tot += (int64_t)b.grid * (int64_t)wave_ws_floats_host(b.R / b.tw, b.pmax, b.nlds, b.tw);
     }
     if (tot > pl->wws_floats || (tot > 0 && !pl->d_wws)) {
         (void)hipFree(pl->d_wws);
@@ -470,12 +495,14 @@ static int layout_workspace(ladl_plan_t pl)
     return LADL_OK;
 }
 
-static void set_schedule(ladl_plan_t pl, Bucket &b, bool xg, bool dense)
+static void set_schedule(ladl_plan_t pl, Bucket &b, bool xg, bool dense, int tw)
 {
-    b.xg = xg || dense;
-    b.dense = dense && wave_has_dense(b.R);
+    b.tw = wave_has_team(b.R, tw) ? tw : 1;
+    b.xg = xg || dense || b.tw > 1;
+    b.dense = dense && b.tw == 1 && wave_has_dense(b.R);
     b.nlds = b.xg ? 0 : b.pmax;
-    b.per_cu = std::max(1, wave_max_blocks_per_cu(b.R, b.pmax, b.xg, b.dense, b.nlds));
+    const int Rw = b.R / b.tw; // row slots per lane of each wave
+    b.per_cu = std::max(1, wave_max_blocks_per_cu(b.R, b.pmax, b.xg, b.dense, b.tw, b.nlds));
     // With the workspace, keep in LDS as many leading columns of X as the
     // LDS left over at this occupancy holds.  Where buckets run side by side
     // that LDS is what lets the other buckets' waves share a CU, so there
@@ -484,8 +511,8 @@ static void set_schedule(ladl_plan_t pl, Bucket &b, bool xg, bool dense)
     // subsets of the correlated dataset 8% slower when every bucket took
     // them).
     const bool take = !pl->multi_bucket || b.R >= 32;
-    while (take && b.xg && b.nlds < b.pmax && wave_lds_bytes(b.R, b.pmax, true, b.nlds + 1) <= pl->h->lds_max &&
-           wave_max_blocks_per_cu(b.R, b.pmax, true, b.dense, b.nlds + 1) >= b.per_cu)
+    while (take && b.xg && b.nlds < b.pmax && wave_lds_bytes(Rw, b.pmax, true, b.nlds + 1, b.tw) <= pl->h->lds_max &&
+           wave_max_blocks_per_cu(b.R, b.pmax, true, b.dense, b.tw, b.nlds + 1) >= b.per_cu)
         ++b.nlds;
     b.grid = (int)std::min<int64_t>(b.count, (int64_t)b.per_cu * pl->h->num_cu);
 }
@@ -501,15 +528,16 @@ static hipError_t launch_bucket(ladl_plan_t pl, size_t bi, const SolveArgs &base
     a.nlds = bk.nlds;
     if (bk.xg) {
         a.gws = pl->d_wws + bk.ws_off;
-        a.gws_stride = (int64_t)wave_ws_floats_host(bk.R, bk.pmax, bk.nlds);
+        a.gws_stride = (int64_t)wave_ws_floats_host(bk.R / bk.tw, bk.pmax, bk.nlds, bk.tw);
     }
-    return launch_wave(bk.R, bk.xg, bk.dense, a, bk.grid, s);
+    return launch_wave(bk.R, bk.xg, bk.dense, bk.tw, a, bk.grid, s);
 }
 
 static int enqueue_wave(ladl_plan_t pl, const float *X, const float *y, const float *lam, const float *b_init,
                         float *b, float *obj, uint32_t *active, int32_t *zr, int32_t *st, int32_t *it, int t0,
-                        int t1, hipStream_t s)
+                        int t1, hipStream_t s, bool capturing = false)
 {
+    const bool timed = pl->profiling && !capturing;
     hipError_t e = launch_reset(pl->d_counters, (int)pl->buckets.size(), s);
     if (e != hipSuccess) return hipfail(e, "queue reset launch");
     const bool fork = pl->buckets.size() > 1;
@@ -519,8 +547,21 @@ static int enqueue_wave(ladl_plan_t pl, const float *X, const float *y, const fl
         hipStream_t bs = fork ? pl->bstreams[bi] : s;
         if (fork && (e = hipStreamWaitEvent(bs, pl->ev_fork, 0)) != hipSuccess) return hipfail(e, "fork wait");
         (void)bk;
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        if (timed) {
+            if ((e = hipEventCreate(&ev.first)) != hipSuccess || (e = hipEventCreate(&ev.second)) != hipSuccess ||
+                (e = hipEventRecord(ev.first, bs)) != hipSuccess) {
+                if (ev.first) (void)hipEventDestroy(ev.first);
+                if (ev.second) (void)hipEventDestroy(ev.second);
+                return hipfail(e, "profiling event");
+            }
+        }
         e = launch_bucket(pl, bi, base_args(pl, X, y, lam, b_init, b, obj, active, zr, st, it, t0, t1), bs);
         if (e != hipSuccess) return hipfail(e, "solve kernel launch");
+        if (timed) {
+            if ((e = hipEventRecord(ev.second, bs)) != hipSuccess) return hipfail(e, "profiling event");
+            pl->prof[bi].push_back(ev);
+        }
         if (fork && (e = hipEventRecord(pl->ev_join[bi], bs)) != hipSuccess) return hipfail(e, "join event");
     }
     for (size_t bi = 0; fork && bi < pl->buckets.size(); ++bi)
@@ -621,7 +662,7 @@ int ladl_graph_create(ladl_plan_t pl, const float *X, const float *y, const floa
     }
     // one launch per path step, each warm-started from the previous output
     for (int t = 0; t < pl->L && rc == LADL_OK; ++t)
-        rc = enqueue_wave(pl, X, y, lam, b_init, b, obj, active, zr, st, it, t, t + 1, g->cap);
+        rc = enqueue_wave(pl, X, y, lam, b_init, b, obj, active, zr, st, it, t, t + 1, g->cap, true);
     hipGraph_t gr = nullptr;
     e = hipStreamEndCapture(g->cap, &gr);
     g->graph = gr;
@@ -707,21 +748,35 @@ int ladl_autotune(ladl_plan_t pl, const float *X, const float *y, const float *l
         return hipfail(e, "tuning events");
     }
     // candidates per bucket: 0 = X in LDS, 1 = X in the HBM workspace,
-    // 2 = the HBM workspace with the dense kernel variant
+    // 2 = the HBM workspace with the dense kernel variant, 3 and 4 = the HBM
+    // workspace with a team of 2 or 4 waves per solve
+    auto apply = [&](Bucket &bk, int v) { set_schedule(pl, bk, v != 0, v == 2, v == 3 ? 2 : (v == 4 ? 4 : 1)); };
     for (size_t bi = 0; bi < pl->buckets.size() && rc == LADL_OK; ++bi) {
         Bucket &bk = pl->buckets[bi];
-        const bool can_lds = bk.R < 32 && wave_lds_bytes(bk.R, bk.pmax, false, 0) <= pl->h->lds_max;
-        const bool can_dense = wave_has_dense(bk.R);
-        if (!can_lds && !can_dense) continue; // only the workspace schedule exists
+        const int forced = pl->opt.team; // 0: the team size is tuned too
+        bool can[5];
+        can[0] = bk.R < 32 && wave_lds_bytes(bk.R, bk.pmax, false, 0, 1) <= pl->h->lds_max;
+        can[1] = true;
+        can[2] = wave_has_dense(bk.R);
+        can[3] = wave_has_team(bk.R, 2);
+        can[4] = wave_has_team(bk.R, 4);
+        for (int v = 0; v < 5; ++v) {
+            const int tw = v == 3 ? 2 : (v == 4 ? 4 : 1);
+            if (forced > 0 && tw != forced) can[v] = false;
+        }
+        int ncand = 0;
+        for (int v = 0; v < 5; ++v) ncand += can[v] ? 1 : 0;
+        if (ncand < 2) continue; // nothing to choose
         int cached = cache_lookup(dev, bk.R, bk.pmax);
-        if (cached >= 0 && cached <= 2 && (cached != 0 || can_lds) && (cached != 2 || can_dense)) {
-            set_schedule(pl, bk, cached != 0, cached == 2);
+        if (cached >= 0 && cached <= 4 && can[cached]) {
+            apply(bk, cached);
             continue;
         }
         float best_ms = 1e30f;
-        int best_v = bk.dense ? 2 : (bk.xg ? 1 : 0);
-        for (int v = can_lds ? 0 : 1; v < (can_dense ? 3 : 2) && rc == LADL_OK; ++v) {
-            set_schedule(pl, bk, v != 0, v == 2);
+        int best_v = bk.tw == 4 ? 4 : (bk.tw == 2 ? 3 : (bk.dense ? 2 : (bk.xg ? 1 : 0)));
+        for (int v = 0; v < 5 && rc == LADL_OK; ++v) {
+            if (!can[v]) continue;
+            apply(bk, v);
             if ((rc = layout_workspace(pl)) != LADL_OK) break;
             SolveArgs a = base_args(pl, X, y, lam, nullptr, b, obj, active, zr, st, nullptr, 0, pl->L);
             float ms = 0.f;
@@ -740,7 +795,7 @@ int ladl_autotune(ladl_plan_t pl, const float *X, const float *y, const float *l
             }
         }
         if (rc == LADL_OK) {
-            set_schedule(pl, bk, best_v != 0, best_v == 2);
+            apply(bk, best_v);
             cache_store(dev, bk.R, bk.pmax, best_v);
         }
     }
@@ -748,6 +803,39 @@ int ladl_autotune(ladl_plan_t pl, const float *X, const float *y, const float *l
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+int ladl_plan_profile(ladl_plan_t pl, int32_t enable)
+{
+    if (!pl) return fail(LADL_EINVAL, "plan is NULL");
+    prof_clear(pl);
+    pl->profiling = enable != 0;
+    if (pl->profiling) pl->prof.resize(pl->buckets.size());
+    return LADL_OK;
+}
+
+int ladl_plan_profile_read(ladl_plan_t pl, float *ms, int32_t *launches, int32_t max_buckets, int32_t *num_buckets)
+{
+    if (!pl || !ms || !launches || !num_buckets) return fail(LADL_EINVAL, "a required pointer is NULL");
+    const int nb = (int)pl->buckets.size();
+    *num_buckets = nb;
+    if (max_buckets < nb) return fail(LADL_EINVAL, "max_buckets %d < %d buckets", max_buckets, nb);
+    for (int bi = 0; bi < nb; ++bi) {
+        double acc = 0.0;
+        int cnt = 0;
+        if (bi < (int)pl->prof.size())
+            for (auto &ev : pl->prof[bi]) {
+                float t = 0.f;
+                hipError_t e = hipEventSynchronize(ev.second);
+                if (e == hipSuccess) e = hipEventElapsedTime(&t, ev.first, ev.second);
+                if (e != hipSuccess) return hipfail(e, "profiling event");
+                acc += t;
+                ++cnt;
+            }
+        ms[bi] = (float)acc;
+        launches[bi] = cnt;
+    }
+    return LADL_OK;
 }
 
 int ladl_plan_describe(ladl_plan_t pl, char *buf, int64_t len)
@@ -764,8 +852,10 @@ int ladl_plan_describe(ladl_plan_t pl, char *buf, int64_t len)
             snprintf(place, sizeof place, "HBM workspace, %d columns in LDS%s", b.nlds, b.dense ? " (dense)" : "");
         else
             snprintf(place, sizeof place, "LDS");
-        snprintf(line, sizeof line, "bucket R=%d (n<=%d) pmax=%d solves=%d grid=%d (%d/CU) X in %s lds=%zuB\n", b.R,
-                 64 * b.R, b.pmax, b.count, b.grid, b.per_cu, place, wave_lds_bytes(b.R, b.pmax, b.xg, b.nlds));
+        snprintf(line, sizeof line,
+                 "bucket R=%d (n<=%d) pmax=%d solves=%d grid=%d (%d/CU) waves/solve=%d X in %s lds=%zuB\n", b.R,
+                 64 * b.R, b.pmax, b.count, b.grid, b.per_cu, b.tw, place,
+                 wave_lds_bytes(b.R / b.tw, b.pmax, b.xg, b.nlds, b.tw));
         s += line;
     }
     std::strncpy(buf, s.c_str(), (size_t)len - 1);

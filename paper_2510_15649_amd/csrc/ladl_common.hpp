@@ -20,10 +20,23 @@ enum { ST_CERTIFIED = 0, ST_NONUNIQUE = 1, ST_MAXITER = 2, ST_NONFINITE = 3, ST_
 constexpr float TOL_U = 2e-5f;   // |u_i| <= 1 + TOL_U on Z
 constexpr float TOL_C = 2e-5f;   // |c_j| <= lambda (1 + TOL_C) + TOL_CA * sum_i |x_ij| off S
 constexpr float TOL_CA = 1e-8f;
-// margins below which a certified vertex is reported as possibly non-unique
-constexpr float MARGIN_U = 1e-3f, MARGIN_C = 1e-3f, MARGIN_R = 1e-5f;
+// Margins below which a certified vertex is reported as possibly
+// non-unique, each against the fp32 error of the quantity it bounds:
+//   1 - max|u_Z| > MARGIN_U          (u_Z refined to ~1e-7 relative)
+//   (lambda - |c_j|) / (lambda + sum_{i in Z} |x_ij|) > MARGIN_C, j off S
+//                                    (c_j takes the error of u_Z through
+//                                     the vertex rows' entries only; the
+//                                     other rows enter through exact signs)
+//   |r_i| / (|y_i| + sum_j |x_ij b_j|) > MARGIN_R, rows off Z
+//                                    (b rounded to fp32 moves r_i by about
+//                                     2^-24 sum_j |x_ij b_j|)
+// so a margin above the threshold is resolved by the fp32 computation with
+// a factor of 10 or more to spare.
+constexpr float MARGIN_U = 2e-5f, MARGIN_C = 2e-5f, MARGIN_R = 1e-6f;
 
 constexpr int ALD = 33; // leading dimension of the vertex matrix
+// finisher steps that fail to lower f after which Bland's rule is kept
+constexpr int STALLS_STICKY = 4;
 constexpr int REFINE_MAX = 8; // refinement steps of the vertex and dual solves
 
 #define LADL_INL __device__ __attribute__((always_inline)) inline
@@ -43,7 +56,10 @@ constexpr float PERTURB_REL = 1.52587890625e-05f; // 2^-16
 // H6: ternary chop along axis kax (Sections 3.5-3.6), as a state machine fed
 // with one probe value F(s) at a time so that the solve has a single CCD
 // call site.  F(s) = f after CCD with b_kax := s and axis kax frozen,
-// started from the best point found so far.  The range c +- h,
+// started from the best point found so far.  The centre c = b_kax is
+// probed first: the start point is on the locus of axis-wise minima only
+// when the CCD before the chop converged, which a sweep cap can prevent,
+// and the bracket test below needs F(c) itself.  The range c +- h,
 // h = chop_range * max(1,|c|) (the paper leaves the initial range open and
 // extends it until it holds the minimum), is doubled outward while an end
 // is lower than the centre (clamped to
@@ -66,7 +82,7 @@ LADL_INL void chop_init(Chop &q, float c, float f, float B, float range)
     q.Fc = f;
     q.Flo = q.Fhi = q.F1 = q.F2 = FINF_C;
     q.m1 = q.m2 = 0.f;
-    q.stage = 0;
+    q.stage = -1;
     q.which = 0;
     q.ext = 0;
     q.it = 0;
@@ -82,12 +98,18 @@ LADL_INL bool chop_next(Chop &q, float F, float &s, const DevOpt &opt)
     case 2: q.Fhi = F; break;
     case 3: q.F1 = F; q.have1 = true; break;
     case 4: q.F2 = F; q.have2 = true; break;
+    case 5: q.Fc = F; break;
     default: break;
     }
     const bool golden = (opt.flags & FLAG_GOLDEN) != 0;
     const float g = 0.381966011f;
     for (int guard = 0; guard < 8; ++guard) {
         switch (q.stage) {
+        case -1: // F(c)
+            q.stage = 0;
+            q.which = 5;
+            s = q.c;
+            return true;
         case 0: // F(lo)
             q.stage = 1;
             q.which = 1;

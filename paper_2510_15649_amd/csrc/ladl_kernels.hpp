@@ -28,8 +28,8 @@ struct SolveArgs {
     float *b_out, *obj_out;
     uint32_t *active_out;
     int32_t *zrows_out, *status_out, *iters_out;
-    float *gws;           // plain kernel: per-thread global scratch
-    int64_t gws_stride;   // floats per thread
+    float *gws;           // plain kernel: per-thread global scratch; wave kernel: per-team workspace
+    int64_t gws_stride;   // floats per thread (plain) or per team (wave)
     DevOpt opt;
     int32_t pmax;         // largest p in the bucket (LDS carve-up)
     int32_t nlds;         // with the workspace: columns of X kept in LDS
@@ -72,17 +72,20 @@ struct BruteArgs {
     int64_t *vert_out; // non-singular vertices examined per output, or null
 };
 
-// host-side launchers (defined in ladl_kernels.hip)
-// wave kernel: R = row slots per lane (1..32); xg = X held in a per-wave
-// global workspace instead of LDS (required for R = 32), except its first
-// nlds columns; dense = the variant compiled for 4 waves per SIMD (R <= 4
-// with xg only)
-size_t wave_lds_bytes(int R, int pmax, bool xg, int nlds);
-size_t wave_ws_floats_host(int R, int pmax, int nlds);
-bool wave_has_dense(int R);
-int wave_max_blocks_per_cu(int R, int pmax, bool xg, bool dense, int nlds);
+// host-side launchers (defined with their kernels)
+// wave kernel: Rt = rows per lane of the bucket (1..32, n <= 64 Rt); tw =
+// waves per solve (a team of tw waves, each with Rt / tw row slots per
+// lane); xg = X held in a per-team global workspace instead of LDS
+// (required for Rt = 32), except its first nlds columns; dense = the
+// variant compiled for 4 waves per SIMD (Rt <= 4 with xg, tw = 1).  LDS and
+// workspace sizes take the per-wave R = Rt / tw.
+size_t wave_lds_bytes(int R, int pmax, bool xg, int nlds, int tw);
+size_t wave_ws_floats_host(int R, int pmax, int nlds, int tw);
+bool wave_has_dense(int Rt);
+bool wave_has_team(int Rt, int tw);
+int wave_max_blocks_per_cu(int Rt, int pmax, bool xg, bool dense, int tw, int nlds);
 hipError_t launch_reset(int32_t *counters, int n, hipStream_t s);
-hipError_t launch_wave(int R, bool xg, bool dense, const SolveArgs &a, int grid, hipStream_t s);
+hipError_t launch_wave(int Rt, bool xg, bool dense, int tw, const SolveArgs &a, int grid, hipStream_t s);
 hipError_t launch_plain(const SolveArgs &a, int NM, int64_t nthreads, hipStream_t s);
 int64_t plain_scratch_floats(int NM, int64_t nthreads);
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);

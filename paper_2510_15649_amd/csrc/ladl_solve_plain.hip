@@ -36,6 +36,7 @@ struct PT {
     IA<int> kid, zf, zs, ss, piv;
     IA<double> gd;
     int c_sweeps, c_updates, c_probes, c_pivots;
+    double fv64; // objective of the last evaluated vertex, fp64 residual sums
     __device__ __forceinline__ float x(int i, int j) const { return X[(int64_t)i * p + j]; }
 };
 
@@ -361,11 +362,15 @@ __device__ bool pt_vertex_eval(PT &t, int s, float &f)
         t.bt[t.ss[c]] = bc;
     }
     // residuals in fp64 (stored as fp32): the certificate reads their signs
+    double s64 = 0.0;
     for (int i = 0; i < t.n; ++i) {
         double r = (double)t.y[i];
         for (int c = 0; c < s; ++c) r = fma(-(double)t.x(i, t.ss[c]), (double)t.bt[t.ss[c]], r);
         t.rv[i] = t.zf[i] ? 0.f : (float)r;
+        s64 += t.zf[i] ? 0.0 : fabs(r);
     }
+    for (int c = 0; c < s; ++c) s64 += (double)t.lam * fabs((double)t.bt[t.ss[c]]);
+    t.fv64 = s64;
     f = pt_objective(t, t.rv, t.bt);
     return true;
 }
@@ -408,18 +413,28 @@ __device__ bool pt_certificate(PT &t, int s, float *u, float *c, bool &unique)
     float mc = FINF_C;
     for (int j = 0; j < p; ++j) {
         double cj = t.gd[j];
-        for (int q = 0; q < s; ++q) cj += (double)t.x(t.zs[q], j) * (double)u[q];
+        float colz = 0.f; // sum_{i in Z} |x_ij|
+        for (int q = 0; q < s; ++q) {
+            const float xv = t.x(t.zs[q], j);
+            cj += (double)xv * (double)u[q];
+            colz += fabsf(xv);
+        }
         c[j] = (float)cj;
         if ((smask >> j) & 1u) continue;
         float cabs = fabsf(c[j]), colabs = t.ca[j];
         if (cabs > t.lam * (1.f + TOL_C) + TOL_CA * colabs) viol = true;
-        mc = fminf(mc, (t.lam - cabs) / (t.lam + colabs));
+        mc = fminf(mc, (t.lam - cabs) / (t.lam + colz));
     }
     const bool cert = umax <= 1.f + TOL_U && !viol;
+    // rows off Z: |r_i| against |y_i| + sum_{j in S} |x_ij b_j|
     float mr = FINF_C;
-    for (int i = 0; i < n; ++i)
-        if (!t.zf[i] && t.rn[i] > 0.f) mr = fminf(mr, fabsf(t.rv[i]) / t.rn[i]);
-    unique = cert && (1.f - umax > MARGIN_U) && (mc > MARGIN_C) && (mr > MARGIN_R * (1.f + t.ynorm1 / n));
+    for (int i = 0; i < n; ++i) {
+        if (t.zf[i]) continue;
+        float sc = fabsf(t.y[i]);
+        for (int q = 0; q < s; ++q) sc = fmaf(fabsf(t.x(i, t.ss[q])), fabsf(t.bt[t.ss[q]]), sc);
+        mr = fminf(mr, (sc > 0.f) ? fabsf(t.rv[i]) / sc : fabsf(t.rv[i]));
+    }
+    unique = cert && (1.f - umax > MARGIN_U) && (mc > MARGIN_C) && (mr > MARGIN_R);
     return cert;
 }
 
@@ -433,27 +448,36 @@ __device__ int pt_finisher(PT &t, int &s, float &f, float *u, float *c, bool &un
 {
     const int n = t.n, p = t.p;
     const float lam = t.lam;
+    double fprev = __builtin_inf();
+    int stalls = 0;
     for (int it = 0;; ++it) {
         pt_set_zf(t, s);
         if (!pt_vertex_eval(t, s, f)) return ST_NOTCERT;
         if (pt_certificate(t, s, u, c, unique)) return unique ? ST_CERTIFIED : ST_NONUNIQUE;
         if (it >= maxp) return ST_MAXITER;
+        // steepest violated constraint, the violated one of lowest index
+        // (Bland's rule) after a step that did not lower f (fp64), and Bland's
+        // rule for the rest once STALLS_STICKY steps have stalled
+        const bool stalled = !(t.fv64 < fprev - 1e-9 * fabs(fprev));
+        stalls += stalled ? 1 : 0;
+        const bool bland = stalled || stalls >= STALLS_STICKY;
+        fprev = t.fv64;
         uint32_t smask = 0;
         for (int q = 0; q < s; ++q) smask |= 1u << t.ss[q];
         float best = FINF_C;
         int type = 0, sel = -1;
         for (int q = 0; q < s; ++q) {
             float sl = 1.f - fabsf(u[q]);
-            if (sl < -TOL_U && sl < best) {
+            if (sl < -TOL_U && (bland ? (sel < 0 || t.zs[q] < t.zs[sel]) : sl < best)) {
                 best = sl;
                 type = 1;
                 sel = q;
             }
         }
-        for (int j = 0; j < p; ++j) {
+        for (int j = 0; j < p && !(bland && sel >= 0); ++j) {
             if ((smask >> j) & 1u) continue;
             float sl = lam - fabsf(c[j]);
-            if (fabsf(c[j]) > lam * (1.f + TOL_C) + TOL_CA * t.ca[j] && sl < best) {
+            if (fabsf(c[j]) > lam * (1.f + TOL_C) + TOL_CA * t.ca[j] && (bland ? sel < 0 : sl < best)) {
                 best = sl;
                 type = 2;
                 sel = j;

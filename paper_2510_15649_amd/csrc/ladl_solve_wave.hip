@@ -1,6 +1,7 @@
-// Forward LAD-LASSO solve: one wavefront per solve, persistent grid with an
-// atomic work queue, problem data in LDS (or partly in a per-wave HBM
-// workspace for the larger buckets).
+// Forward LAD-LASSO solve: one solve per wavefront, or per team of TW
+// wavefronts of one workgroup, in a persistent grid with an atomic work
+// queue; problem data in LDS (or partly in a per-team HBM workspace for the
+// larger buckets).
 //
 // Per solve (Abstract; Sections 3.3-3.6 of the paper, plus a vertex
 // certificate and simplex finisher that the paper does not have):
@@ -14,73 +15,114 @@
 //      minimum (Sections 3.5-3.6); polish, snap and certify again;
 //   4. primal simplex steps along the vertex's edges until certified.
 //
-// Layout in LDS (floats), per wave:
-//   Xs  p columns of LDN = 64R+1 floats; row i of column j at j*LDN + i,
-//       row i owned by lane i%64, register slot i/64 (rows >= n are 0)
-//   ys  y, LDN floats (row norms ||x_i||_2 are recomputed where needed)
+// Rows.  With RT = 64 TW rows per register slot, row i belongs to wave
+// (i / 64) mod TW, lane i mod 64, slot i / RT: each slot of a wave covers 64
+// consecutive rows, so column reads stay coalesced.  Every reduction over
+// rows is a team reduction (ladl_team.hpp); b, the chop state and the vertex
+// algebra are replicated in every wave and updated identically.
+//
+// Layout in LDS (floats), per team:
+//   shared: team exchange slots; sa/sw (compaction), the sample exchange;
+//       Xs: p columns of LDN = 64 R TW + 1 floats, row i of column j at
+//       j*LDN + i (rows >= n are 0); ys: y, LDN floats
+//   per wave: gd (32 doubles), best residuals (64 R), A (vertex matrix / LU,
+//       pmax rows of 33), A0 (unfactored, pmax x (pmax+1)), six vectors of
+//       32 (b, best b, column |x| sums, direction, scratch), zs/ss/piv, the
+//       chop state
 // With the HBM workspace (XG), only the first nlds columns stay in LDS (as
-// many as the LDS left over at the kernel's register-bound occupancy
-// holds); the other columns and y live in the wave's workspace slice, in
-// the same column layout.
-//   A   vertex matrix / LU factors, pmax rows of 33
-//   A0  the vertex matrix unfactored (refinement residuals), pmax x (pmax+1)
-//   small vectors of 32 (b, best b, column |x| sums, direction, scratch)
-//   gd  32 doubles (certificate), sa/sw 64+64 (selection compaction)
+// many as the LDS left over at the kernel's occupancy holds); the other
+// columns and y live in the team's workspace slice, in the same layout.
 #include "ladl_common.hpp"
 #include "ladl_kernels.hpp"
+#include "ladl_team.hpp"
 #include "ladl_wave.hpp"
 
 #include <climits>
 
 namespace ladl {
 
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float unif(float v) { return bitsf(__builtin_amdgcn_readfirstlane(fbits(v))); }
+__host__ __device__ constexpr int wave_ldn(int R, int TW) { return 64 * R * TW + 1; }
 
-__host__ __device__ constexpr int wave_ldn(int R) { return 64 * R + 1; }
-
-// LDS floats per wave: gd, [Xs, ys when resident; the first nlds columns
-// of Xs with the workspace], best residuals, A (pmax rows), A0, 6 vectors,
-// sa/sw, zs/ss/piv, the chop state
 constexpr int CHOP_FLOATS = 32;
-__host__ __device__ constexpr size_t wave_lds_floats(int R, int pmax, bool xg, int nlds)
+// LDS floats shared by a team: exchange slots, sa/sw, samples, queue word
+__host__ __device__ constexpr size_t team_shared_floats(int TW)
 {
-    return 64 + (size_t)(xg ? nlds : pmax + 1) * wave_ldn(R) + 64 * (size_t)R + (size_t)pmax * ALD +
-           (size_t)pmax * (pmax + 1) + 6 * 32 + 128 + 3 * 32 + CHOP_FLOATS;
+    return (size_t)team_red_words(TW) + 128 + (TW > 1 ? 64 * TW : 0) + 4;
 }
-// global workspace floats per wave with the workspace: columns nlds .. p-1
-// of Xs, then ys
-__host__ __device__ constexpr size_t wave_ws_floats(int R, int pmax, int nlds)
+// LDS floats private to each wave (a multiple of 4, so every wave's gd
+// stays 16-byte aligned)
+__host__ __device__ constexpr size_t wave_private_floats(int R, int pmax)
 {
-    return (size_t)(pmax + 1 - nlds) * wave_ldn(R);
+    return ((64 + 64 * (size_t)R + (size_t)pmax * ALD + (size_t)pmax * (pmax + 1) + 6 * 32 + 3 * 32 + CHOP_FLOATS) +
+            3) & ~(size_t)3;
+}
+// LDS floats per team: shared part, [Xs, ys when resident; the first nlds
+// columns of Xs with the workspace], TW private parts
+__host__ __device__ constexpr size_t wave_lds_floats(int R, int pmax, bool xg, int nlds, int TW)
+{
+    return team_shared_floats(TW) + (size_t)(xg ? nlds : pmax + 1) * wave_ldn(R, TW) +
+           (size_t)TW * wave_private_floats(R, pmax);
+}
+// global workspace floats per team with the workspace: columns nlds .. p-1
+// of Xs, then ys
+__host__ __device__ constexpr size_t wave_ws_floats(int R, int pmax, int nlds, int TW)
+{
+    return (size_t)(pmax + 1 - nlds) * wave_ldn(R, TW);
 }
 
-template <int R, bool XG>
+template <int R, bool XG, int TW>
 struct Wave {
-    static constexpr int LDN = wave_ldn(R);
+    static constexpr int LDN = wave_ldn(R, TW);
+    static constexpr int RT = 64 * TW; // rows per register slot of the team
     // Xs: the LDS columns of X (all of them without the workspace); Xg: the
     // workspace columns (column j >= nlds at (j - nlds) * LDN); ys: y, in
     // LDS without the workspace, else after the workspace columns
-    float *Xs, *Xg, *ys, *rbuf, *A, *A0, *vb, *vbb, *vca, *vd, *vg, *vt, *sa, *sw;
+    float *Xs, *Xg, *ys, *rbuf, *A, *A0, *vb, *vbb, *vca, *vd, *vg, *vt, *sa, *sw, *smp;
     double *gd;
-    int *zs, *ss, *piv;
-    // the ternary chop's state (wave-uniform): kept in LDS rather than in
-    // VGPRs that would be live across every probe's CCD
+    int *zs, *ss, *piv, *qw;
+    // the ternary chop's state (uniform): kept in LDS rather than in VGPRs
+    // that would be live across every probe's CCD
     Chop *chop;
+    Team<TW> tm;
+    int wv, rb;   // wave in the team; row of this lane in slot 0 (64 wv + lane)
     int n, p, nslot, a0ld, nlds;
     float lam, ynorm1;
     float cav; // lane j: sum_i |x_ij|
     DevOpt opt;
     int c_sweeps, c_updates, c_probes, c_pivots;
+    double fv64; // objective of the last evaluated vertex, fp64 residual sums
 };
 
-template <int R, bool XG>
-LADL_INL void carve(Wave<R, XG> &w, float *smem, int pmax, int nlds, float *ws)
+// the team row of register slot k of this lane
+template <int R, bool XG, int TW>
+__device__ __forceinline__ int row_of(const Wave<R, XG, TW> &w, int k)
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
-    float *q = smem;
-    w.gd = (double *)q; // first: the dynamic LDS base is 16-byte aligned
+    return Wave<R, XG, TW>::RT * k + w.rb;
+}
+// wave, slot and lane that hold team row i
+__device__ __forceinline__ int row_wave(int i, int TW) { return (i >> 6) % TW; }
+__device__ __forceinline__ int row_slot(int i, int TW) { return i / (64 * TW); }
+
+template <int R, bool XG, int TW>
+LADL_INL void carve(Wave<R, XG, TW> &w, float *smem, int pmax, int nlds, float *ws, int wv)
+{
+    constexpr int LDN = Wave<R, XG, TW>::LDN;
+    float *q = smem; // the dynamic LDS base is 16-byte aligned
+    w.wv = wv;
+    w.rb = 64 * wv + lane_id();
+    w.tm.wv = wv;
+    w.tm.seq = 0;
+    w.tm.red = q;
+    w.tm.vec = (double *)(q + 16 * TW);
+    q += team_red_words(TW);
+    w.sa = q;
     q += 64;
+    w.sw = q;
+    q += 64;
+    w.smp = q;
+    q += (TW > 1 ? 64 * TW : 0);
+    w.qw = (int *)q;
+    q += 4;
     w.Xs = q;
     if (XG) {
         w.nlds = nlds;
@@ -94,6 +136,13 @@ LADL_INL void carve(Wave<R, XG> &w, float *smem, int pmax, int nlds, float *ws)
         w.ys = q;
         q += LDN;
     }
+    // this wave's private part (a multiple of 4 floats from a 16-byte
+    // aligned start: team_shared_floats and LDN-sized blocks keep q aligned
+    // to 4 bytes only, so round up)
+    q = (float *)(((uintptr_t)q + 15) & ~(uintptr_t)15);
+    q += (size_t)wv * wave_private_floats(R, pmax);
+    w.gd = (double *)q;
+    q += 64;
     w.rbuf = q;
     q += 64 * R;
     w.A = q;
@@ -113,10 +162,6 @@ LADL_INL void carve(Wave<R, XG> &w, float *smem, int pmax, int nlds, float *ws)
     q += 32;
     w.vt = q;
     q += 32;
-    w.sa = q;
-    q += 64;
-    w.sw = q;
-    q += 64;
     w.zs = (int *)q;
     q += 32;
     w.ss = (int *)q;
@@ -126,9 +171,9 @@ LADL_INL void carve(Wave<R, XG> &w, float *smem, int pmax, int nlds, float *ws)
     w.chop = (Chop *)q;
 }
 
-// After this wave writes its workspace (global memory when XG): the stores
-// complete, and L1 drops lines it may hold from before, so the wave's next
-// loads see what it wrote.  With LDS only the wave barrier is needed.
+// After the team writes its workspace (global memory when XG): the stores
+// complete, and L1 drops lines it may hold from before, so the next loads
+// see what was written.  With LDS only the barrier is needed.
 template <bool XG>
 LADL_INL void ws_sync()
 {
@@ -144,74 +189,75 @@ LADL_INL void ws_sync()
 // LDS or a global load, for smaller R one generic load of the selected
 // address (measured on the ragged workload: the branch form made the
 // n <= 2048 bucket 1.5x faster and the n <= 512 and n <= 1024 buckets 5%
-// slower).  And the wave's R elements of a column j that is the same on
+// slower).  And this lane's R elements of a column j that is the same on
 // every lane, from LDS (j < nlds) or from the workspace (j >= nlds).
 typedef __attribute__((address_space(3))) float lds_f32;
 typedef __attribute__((address_space(1))) float glb_f32;
 
-template <int R, bool XG>
-LADL_INL const float *xaddr(const Wave<R, XG> &w, int j)
+template <int R, bool XG, int TW>
+LADL_INL const float *xaddr(const Wave<R, XG, TW> &w, int j)
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
+    constexpr int LDN = Wave<R, XG, TW>::LDN;
     return (j < w.nlds) ? w.Xs + j * LDN : w.Xg + (j - w.nlds) * LDN;
 }
 
-template <int R, bool XG>
-LADL_INL float xget(const Wave<R, XG> &w, int j, int idx)
+template <int R, bool XG, int TW>
+LADL_INL float xget(const Wave<R, XG, TW> &w, int j, int idx)
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
+    constexpr int LDN = Wave<R, XG, TW>::LDN;
     if (!XG) return ((const lds_f32 *)w.Xs)[j * LDN + idx];
-    if (R >= 32) {
+    if (R * TW >= 32) {
         if (j < w.nlds) return ((const lds_f32 *)w.Xs)[j * LDN + idx];
         return ((const glb_f32 *)w.Xg)[(j - w.nlds) * LDN + idx];
     }
     return xaddr(w, j)[idx];
 }
 
-template <int R, bool XG>
-LADL_INL void xput(Wave<R, XG> &w, int j, int idx, float v)
+template <int R, bool XG, int TW>
+LADL_INL void xput(Wave<R, XG, TW> &w, int j, int idx, float v)
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
+    constexpr int LDN = Wave<R, XG, TW>::LDN;
     if (!XG || j < w.nlds)
         ((lds_f32 *)w.Xs)[j * LDN + idx] = v;
     else
         ((glb_f32 *)w.Xg)[(j - w.nlds) * LDN + idx] = v;
 }
 
-template <int R, bool XG>
-LADL_INL void xcol_lds(const Wave<R, XG> &w, int j, float (&x)[R])
+template <int R, bool XG, int TW>
+LADL_INL void xcol_lds(const Wave<R, XG, TW> &w, int j, float (&x)[R])
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
-    const lds_f32 *c = (const lds_f32 *)w.Xs + j * LDN + lane_id();
+    constexpr int LDN = Wave<R, XG, TW>::LDN, RT = Wave<R, XG, TW>::RT;
+    const lds_f32 *c = (const lds_f32 *)w.Xs + j * LDN + w.rb;
 #pragma unroll
-    for (int k = 0; k < R; ++k) x[k] = c[64 * k];
+    for (int k = 0; k < R; ++k) x[k] = c[RT * k];
 }
 
-template <int R, bool XG>
-LADL_INL void xcol_ws(const Wave<R, XG> &w, int j, float (&x)[R])
+template <int R, bool XG, int TW>
+LADL_INL void xcol_ws(const Wave<R, XG, TW> &w, int j, float (&x)[R])
 {
-    constexpr int LDN = Wave<R, XG>::LDN;
-    const glb_f32 *c = (const glb_f32 *)w.Xg + (j - w.nlds) * LDN + lane_id();
+    constexpr int LDN = Wave<R, XG, TW>::LDN, RT = Wave<R, XG, TW>::RT;
+    const glb_f32 *c = (const glb_f32 *)w.Xg + (j - w.nlds) * LDN + w.rb;
 #pragma unroll
-    for (int k = 0; k < R; ++k) x[k] = c[64 * k];
+    for (int k = 0; k < R; ++k) x[k] = c[RT * k];
 }
 
 // --------------------------------------------------------------------------
 // problem load: X row-major in HBM -> column-major in LDS (coalesced reads)
 // --------------------------------------------------------------------------
-template <int R, bool XG>
-LADL_INL bool load_problem(Wave<R, XG> &w, const float *__restrict__ X, const float *__restrict__ y)
+template <int R, bool XG, int TW>
+LADL_INL bool load_problem(Wave<R, XG, TW> &w, const float *__restrict__ X, const float *__restrict__ y)
 {
-    // rows n .. 64R-1 are zero padding (so hot loops read all R slots
+    // rows n .. RT R - 1 are zero padding (so hot loops read all R slots
     // without guards: a zero row has a zero residual and no weight)
-    const int l = lane_id(), n = w.n, p = w.p, top = 64 * R;
+    constexpr int RT = Wave<R, XG, TW>::RT;
+    const int l = lane_id(), tl = w.rb, n = w.n, p = w.p, top = RT * R;
     for (int j = 0; j < p; ++j)
-        for (int i = n + l; i < top; i += 64) xput(w, j, i, 0.f);
-    for (int i = n + l; i < top; i += 64) w.ys[i] = 0.f;
+        for (int i = n + tl; i < top; i += RT) xput(w, j, i, 0.f);
+    for (int i = n + tl; i < top; i += RT) w.ys[i] = 0.f;
     bool finite = true;
     const int np = n * p;
     const float invp = 1.0f / (float)p;
-    for (int e = l; e < np; e += 64) {
+    for (int e = tl; e < np; e += RT) {
         float v = X[e];
         int i = (int)((float)e * invp);
         if (i * p > e)
@@ -221,97 +267,155 @@ LADL_INL bool load_problem(Wave<R, XG> &w, const float *__restrict__ X, const fl
         xput(w, e - i * p, i, v);
         finite = finite && __builtin_isfinite(v);
     }
-    for (int i = l; i < n; i += 64) {
+    for (int i = tl; i < n; i += RT) {
         float v = y[i];
         w.ys[i] = v;
         finite = finite && __builtin_isfinite(v);
     }
     ws_sync<XG>();
+    float mine = 0.f;
     for (int j = 0; j < p; ++j) {
         float part = 0.f;
-        for (int i = l; i < n; i += 64) part += fabsf(xget(w, j, i));
-        float sj = wsum(part);
-        if (l == j) w.vca[j] = sj;
-        if (l == j) w.cav = sj;
+        for (int i = tl; i < n; i += RT) part += fabsf(xget(w, j, i));
+        const float sj = wsum(part);
+        mine = (l == j) ? sj : mine;
     }
-    if (l >= p) w.cav = 0.f;
+    const float cs = (TW == 1) ? mine : (float)tsum_vec_d(w.tm, (double)mine);
+    w.cav = (l < p) ? cs : 0.f;
+    if (l < p) w.vca[l] = cs;
     float yp = 0.f;
-    for (int i = l; i < n; i += 64) yp += fabsf(w.ys[i]);
-    w.ynorm1 = wsum(yp);
+    for (int i = tl; i < n; i += RT) yp += fabsf(w.ys[i]);
+    w.ynorm1 = tsum(w.tm, yp);
     __syncthreads();
-    return ballot(!finite) == 0;
+    return tcount(w.tm, !finite) == 0;
 }
 
 // r = y - X b, b held one coefficient per lane (lane j: b_j)
-template <int R, bool XG>
-LADL_INL void residuals(Wave<R, XG> &w, float (&r)[R], float bv)
+template <int R, bool XG, int TW>
+LADL_INL void residuals(Wave<R, XG, TW> &w, float (&r)[R], float bv)
 {
-    const int l = lane_id();
 #pragma unroll
-    for (int k = 0; k < R; ++k) r[k] = (k < w.nslot) ? w.ys[64 * k + l] : 0.f;
+    for (int k = 0; k < R; ++k) r[k] = (k < w.nslot) ? w.ys[row_of(w, k)] : 0.f;
     for (int j = 0; j < w.p; ++j) {
         float bj = rdlane(bv, j);
         if (bj != 0.f) {
 #pragma unroll
             for (int k = 0; k < R; ++k)
-                if (k < w.nslot) r[k] = fmaf(-xget(w, j, 64 * k + l), bj, r[k]);
+                if (k < w.nslot) r[k] = fmaf(-xget(w, j, row_of(w, k)), bj, r[k]);
         }
     }
 }
 
-// f = sum |r_i| + lambda sum |b_j|, b one coefficient per lane
-template <int R, bool XG>
-LADL_INL float objective(Wave<R, XG> &w, const float (&r)[R], float bval)
+// f = sum |r_i| + lambda sum |b_j|, b one coefficient per lane (the
+// penalty counted by the first wave of the team only)
+template <int R, bool XG, int TW>
+LADL_INL float objective(Wave<R, XG, TW> &w, const float (&r)[R], float bval)
 {
     const int l = lane_id();
     float s = 0.f;
 #pragma unroll
     for (int k = 0; k < R; ++k) s += fabsf(r[k]);
-    float sb = (l < w.p) ? fabsf(bval) : 0.f;
-    wsum2(s, sb);
+    float sb = (w.wv == 0 && l < w.p) ? fabsf(bval) : 0.f;
+    tsum2(w.tm, s, sb);
     return s + w.lam * sb;
 }
 
 // --------------------------------------------------------------------------
-// Weighted selection over the wave.
+// Weighted selection over the team.
 // Candidates: per-lane register keys a[k] (FINF = none) with weights
-// |x[k]| (zero for FINF keys), plus one extra key (av, wv) per lane.  All keys are >= 0.  Returns the
-// smallest key a* whose cumulative weight (over keys <= a*) reaches T
-// (strict: exceeds T), and which register slot or extra key holds it
-// (row keys win ties against extra keys).
+// |x[k]| (zero for FINF keys), plus one extra key (av, wv) per lane (the
+// callers place extra keys in the first wave only).  All keys are >= 0.
+// Returns the smallest key a* whose cumulative weight (over keys <= a*)
+// reaches T (strict: exceeds T), and which wave, register slot or extra
+// key holds it (row keys win ties against extra keys; lower waves, then
+// lower lanes, then lower slots first).
 // --------------------------------------------------------------------------
 struct Sel {
     float a;
-    int lane, slot;
+    int wave, lane, slot;
     bool virt;
 };
 
-template <int R, bool XG>
-LADL_INL Sel owner_of(const float (&a)[R], float av, float m)
+template <int R, bool XG, int TW>
+LADL_INL Sel owner_of(Wave<R, XG, TW> &w, const float (&a)[R], float av, float m)
 {
     int myslot = -1;
 #pragma unroll
     for (int k = R - 1; k >= 0; --k)
         if (a[k] == m) myslot = k;
-    uint64_t rb = ballot(myslot >= 0);
+    const uint64_t rbal = ballot(myslot >= 0);
+    const uint64_t vbal = ballot(av == m);
+    const int rl = rbal ? first_lane(rbal) : -1;
+    const int rs = rbal ? rdlane(myslot, rl) : -1;
+    const int vl = vbal ? first_lane(vbal) : -1;
     Sel s;
     s.a = m;
-    if (rb) {
-        s.lane = first_lane(rb);
-        s.slot = rdlane(myslot, s.lane);
-        s.virt = false;
+    if constexpr (TW == 1) {
+        s.wave = 0;
+        if (rbal) {
+            s.lane = rl;
+            s.slot = rs;
+            s.virt = false;
+        } else {
+            s.lane = vbal ? vl : 0;
+            s.slot = -1;
+            s.virt = true;
+        }
     } else {
-        uint64_t vb = ballot(av == m);
-        s.lane = vb ? first_lane(vb) : 0;
-        s.slot = -1;
-        s.virt = true;
+        int *sl = (int *)team_slot(w.tm);
+        if (lane_id() == 0) {
+            sl[8 * w.wv] = rl;
+            sl[8 * w.wv + 1] = rs;
+            sl[8 * w.wv + 2] = vl;
+        }
+        __syncthreads();
+        int fw = -1, fv = -1;
+#pragma unroll
+        for (int q = TW - 1; q >= 0; --q) {
+            if (sl[8 * q] >= 0) fw = q;
+            if (sl[8 * q + 2] >= 0) fv = q;
+        }
+        fw = uni(fw);
+        fv = uni(fv);
+        if (fw >= 0) {
+            s.wave = fw;
+            s.lane = uni(sl[8 * fw]);
+            s.slot = uni(sl[8 * fw + 1]);
+            s.virt = false;
+        } else {
+            s.wave = fv >= 0 ? fv : 0;
+            s.lane = fv >= 0 ? uni(sl[8 * fv + 2]) : 0;
+            s.slot = -1;
+            s.virt = true;
+        }
     }
     return s;
 }
 
-template <int R, bool XG>
-LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&x)[R], float av, float wv, float T,
-                       bool strict, float lo0, float cum0)
+// number of this wave's keys in (lo, hi], summed over the team
+template <int R, int TW>
+LADL_INL int tcount_range(Team<TW> &t, const float (&a)[R], float av, float lo, float hi)
+{
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) c += popc64(ballot(a[k] > lo && a[k] <= hi));
+    c += popc64(ballot(av > lo && av <= hi));
+    if constexpr (TW == 1) {
+        return c;
+    } else {
+        int *sl = (int *)team_slot(t);
+        if (lane_id() == 0) sl[t.wv] = c;
+        __syncthreads();
+        int s = 0;
+#pragma unroll
+        for (int q = 0; q < TW; ++q) s += sl[q];
+        return uni(s);
+    }
+}
+
+template <int R, bool XG, int TW>
+LADL_INL Sel wselect(Wave<R, XG, TW> &w, const float (&a)[R], const float (&x)[R], float av, float wv, float T,
+                     bool strict, float lo0, float cum0)
 {
     // weights are recomputed where used rather than held in R more registers
     auto wt = [&](int k) { return (a[k] < FINF) ? fabsf(x[k]) : 0.f; };
@@ -324,27 +428,24 @@ LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&x)[R], f
 #pragma unroll
         for (int k = 0; k < R; ++k) m = (a[k] > lo && a[k] < m) ? a[k] : m;
         m = (av > lo && av < m) ? av : m;
-        m = wmin_nn(m);
+        m = tmin_nn(w.tm, m);
         if (m == FINF) {
-            if (lo < 0.f) return Sel{FINF, 0, -1, false}; // no candidate at all
-            return owner_of<R, XG>(a, av, lo);                 // weight exhausted by rounding
+            if (lo < 0.f) return Sel{FINF, 0, 0, -1, false}; // no candidate at all
+            return owner_of(w, a, av, lo);                  // weight exhausted by rounding
         }
         float wm = 0.f;
 #pragma unroll
         for (int k = 0; k < R; ++k) wm += (a[k] == m) ? wt(k) : 0.f;
         wm += (av == m) ? wv : 0.f;
-        wm = wsum(wm);
-        if (reached(cum + wm)) return owner_of<R, XG>(a, av, m);
+        wm = tsum(w.tm, wm);
+        if (reached(cum + wm)) return owner_of(w, a, av, m);
         cum += wm;
         lo = m;
     }
     // Phase B: narrow (lo, hi] around the target with sampled quantiles
     int cnt = 0;
     for (int round = 0; round < 12; ++round) {
-        cnt = 0;
-#pragma unroll
-        for (int k = 0; k < R; ++k) cnt += popc64(ballot(a[k] > lo && a[k] <= hi));
-        cnt += popc64(ballot(av > lo && av <= hi));
+        cnt = tcount_range<R, TW>(w.tm, a, av, lo, hi);
         if (cnt <= 64) break;
         float smp = FINF, wint = 0.f;
 #pragma unroll
@@ -357,7 +458,13 @@ LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&x)[R], f
             smp = (smp == FINF) ? av : smp;
             wint += wv;
         }
-        wint = wsum(wint);
+        wint = tsum(w.tm, wint);
+        if constexpr (TW > 1) {
+            // the same 64 samples on every wave: lane l takes wave (l mod TW)'s
+            w.smp[64 * w.wv + l] = smp;
+            __syncthreads();
+            smp = w.smp[64 * (l % TW) + l];
+        }
         int ns = popc64(ballot(smp < FINF));
         bitonic64(smp);
         float frac = (T - cum) / wint;
@@ -377,7 +484,7 @@ LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&x)[R], f
             c2 += (av <= p2) ? wv : 0.f;
         }
         float z = 0.f;
-        wsum3(c1, c2, z);
+        tsum3(w.tm, c1, c2, z);
         if (reached(cum + c1)) {
             hi = p1;
         } else if (reached(cum + c2)) {
@@ -397,21 +504,34 @@ LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&x)[R], f
             for (int k = 0; k < R; ++k)
                 if (a[k] > lo && a[k] <= hi) m = fminf(m, a[k]);
             if (av > lo && av <= hi) m = fminf(m, av);
-            m = wmin(m);
+            m = tmin(w.tm, m);
             if (m == FINF) break;
             float wm = 0.f;
 #pragma unroll
             for (int k = 0; k < R; ++k) wm += (a[k] == m) ? wt(k) : 0.f;
             wm += (av == m) ? wv : 0.f;
-            wm = wsum(wm);
-            if (reached(cum + wm) || m == hi) return owner_of<R, XG>(a, av, m);
+            wm = tsum(w.tm, wm);
+            if (reached(cum + wm) || m == hi) return owner_of(w, a, av, m);
             cum += wm;
             lo = m;
         }
-        return owner_of<R, XG>(a, av, hi);
+        return owner_of(w, a, av, hi);
     }
-    // Phase C: compact the <= 64 keys of (lo, hi], sort, scan
+    // Phase C: compact the <= 64 keys of (lo, hi] (in team row order), sort,
+    // scan
     int base = 0;
+    if constexpr (TW > 1) {
+        // this wave's first position: the counts of the waves before it
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) c += popc64(ballot(a[k] > lo && a[k] <= hi));
+        c += popc64(ballot(av > lo && av <= hi));
+        int *sl = (int *)team_slot(w.tm);
+        if (l == 0) sl[w.wv] = c;
+        __syncthreads();
+        for (int q = 0; q < w.wv; ++q) base += sl[q];
+        base = uni(base);
+    }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         bool in = a[k] > lo && a[k] <= hi;
@@ -434,8 +554,9 @@ LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&x)[R], f
         base += popc64(bal);
     }
     __syncthreads();
-    float key = (l < base) ? w.sa[l] : FINF;
-    float val = (l < base) ? w.sw[l] : 0.f;
+    const int total = cnt;
+    float key = (l < total) ? w.sa[l] : FINF;
+    float val = (l < total) ? w.sw[l] : 0.f;
     __syncthreads();
     bitonic64(key, val);
     float inc = wscan_incl(val);
@@ -443,11 +564,11 @@ LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&x)[R], f
     float m;
     if (ok)
         m = rdlane(key, first_lane(ok));
-    else if (base > 0)
-        m = rdlane(key, base - 1); // rounding: take the last key
+    else if (total > 0)
+        m = rdlane(key, total - 1); // rounding: take the last key
     else
         m = (hi < FINF) ? hi : lo;
-    return owner_of<R, XG>(a, av, m);
+    return owner_of(w, a, av, m);
 }
 
 // --------------------------------------------------------------------------
@@ -457,10 +578,10 @@ LADL_INL Sel wselect(Wave<R, XG> &w, const float (&a)[R], const float (&x)[R], f
 // signs alone (below: r_i x_ij < 0, at: r_i = 0) and records, per lane, the
 // nearest kink on each side with its weight.  After the two weight sums the
 // direction is known; most moves reach only the nearest kink, decided by
-// one wave minimum.  Longer moves continue in wselect.
+// one wave (team) minimum.  Longer moves continue in wselect.
 // --------------------------------------------------------------------------
-template <int R, bool XG>
-LADL_INL bool coord_update(Wave<R, XG> &w, float (&r)[R], float &bv, int j, const float (&x)[R])
+template <int R, bool XG, int TW>
+LADL_INL bool coord_update(Wave<R, XG, TW> &w, float (&r)[R], float &bv, int j, const float (&x)[R])
 {
     const int l = lane_id();
     // pass 1: weight of the kinks below and at the current b_j (signs only)
@@ -477,7 +598,7 @@ LADL_INL bool coord_update(Wave<R, XG> &w, float (&r)[R], float &bv, int j, cons
         negb |= (uint32_t)neg << k;
     }
     const float bj = rdlane(bv, j);
-    wsum2(bel, at);
+    tsum2(w.tm, bel, at);
     const float lam = w.lam;
     const float W = rdlane(w.cav, j) + lam;
     if (!(W > 0.f)) return false;
@@ -513,36 +634,70 @@ LADL_INL bool coord_update(Wave<R, XG> &w, float (&r)[R], float &bv, int j, cons
     }
     const bool lcand = (lam > 0.f) && (down ? (bj > 0.f) : (bj < 0.f));
     const float al = fabsf(bj);
-    const float m1 = wmin_nn(smin);
-    if (!(m1 < FINF) && !lcand) return false;
-    const float mm = lcand ? fminf(m1, al) : m1;
-    // weight of the nearest kink(s)
-    const uint64_t ob = ballot(smin == mm);
-    float wm = (popc64(ob) > 1) ? wsum((smin == mm) ? sw : 0.f) : (ob ? rdlane(sw, first_lane(ob)) : 0.f);
+    float m1, mm, wm;
+    int owave = 0, olane = -1;
+    if constexpr (TW == 1) {
+        m1 = wmin_nn(smin);
+        if (!(m1 < FINF) && !lcand) return false;
+        mm = lcand ? fminf(m1, al) : m1;
+        // weight of the nearest kink(s)
+        const uint64_t ob = ballot(smin == mm);
+        wm = (popc64(ob) > 1) ? wsum((smin == mm) ? sw : 0.f) : (ob ? rdlane(sw, first_lane(ob)) : 0.f);
+        olane = ob ? first_lane(ob) : -1;
+    } else {
+        // each wave's nearest kink, its weight and first holder, combined in
+        // one exchange
+        const float mloc = wmin_nn(smin);
+        const uint64_t ob = (mloc < FINF) ? ballot(smin == mloc) : 0;
+        const float wl = (mloc < FINF) ? wsum((smin == mloc) ? sw : 0.f) : 0.f;
+        const int fl = ob ? first_lane(ob) : -1;
+        float *sl = team_slot(w.tm);
+        if (l == 0) {
+            sl[8 * w.wv] = mloc;
+            sl[8 * w.wv + 1] = wl;
+            ((int *)sl)[8 * w.wv + 2] = fl;
+        }
+        __syncthreads();
+        m1 = sl[0];
+#pragma unroll
+        for (int q = 1; q < TW; ++q) m1 = fminf(m1, sl[8 * q]);
+        m1 = unif(m1);
+        if (!(m1 < FINF) && !lcand) return false;
+        mm = lcand ? fminf(m1, al) : m1;
+        wm = 0.f;
+        int fw = -1;
+#pragma unroll
+        for (int q = TW - 1; q >= 0; --q)
+            if (sl[8 * q] == mm) fw = q;
+#pragma unroll
+        for (int q = 0; q < TW; ++q) wm += (sl[8 * q] == mm) ? sl[8 * q + 1] : 0.f;
+        wm = unif(wm);
+        fw = uni(fw);
+        owave = fw >= 0 ? fw : 0;
+        olane = fw >= 0 ? uni(((int *)sl)[8 * fw + 2]) : -1;
+    }
     if (lcand && al == mm) wm += lam;
     float nb;
-    int olane = -1, oslot = -1;
+    int oslot = -1;
     bool virt;
     if (reached(wm)) {
-        virt = (ob == 0);
-        if (!virt) {
-            olane = first_lane(ob);
-            oslot = rdlane(sk, olane);
-        }
+        virt = (olane < 0);
+        if (!virt && w.wv == owave) oslot = rdlane(sk, olane);
         nb = virt ? 0.f : (down ? bj - mm : bj + mm);
     } else {
-        const float av = (l == 0 && lcand) ? al : FINF;
-        const float wv = (l == 0 && lcand) ? lam : 0.f;
-        Sel sl = wselect<R, XG>(w, a, x, av, wv, T, down, mm, wm);
+        const float av = (w.wv == 0 && l == 0 && lcand) ? al : FINF;
+        const float wv = (w.wv == 0 && l == 0 && lcand) ? lam : 0.f;
+        Sel sl = wselect(w, a, x, av, wv, T, down, mm, wm);
         if (!(sl.a < FINF)) return false;
         virt = sl.virt;
+        owave = sl.wave;
         olane = sl.lane;
         oslot = sl.slot;
         nb = virt ? 0.f : (down ? bj - sl.a : bj + sl.a);
     }
     const float d = nb - bj;
     if (d == 0.f || !__builtin_isfinite(d)) return false;
-    const bool own = !virt && l == olane;
+    const bool own = !virt && w.wv == owave && l == olane;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const float rn = fmaf(-x[k], d, r[k]);
@@ -553,8 +708,8 @@ LADL_INL bool coord_update(Wave<R, XG> &w, float (&r)[R], float &bv, int j, cons
 }
 
 // H5: cyclic sweeps, axis `frozen` held fixed
-template <int R, bool XG>
-LADL_INL float ccd(Wave<R, XG> &w, float (&r)[R], float &bv, int frozen, float f)
+template <int R, bool XG, int TW>
+LADL_INL float ccd(Wave<R, XG, TW> &w, float (&r)[R], float &bv, int frozen, float f)
 {
     const int p = w.p;
     if (p == 1 && frozen == 0) return f;
@@ -578,7 +733,7 @@ LADL_INL float ccd(Wave<R, XG> &w, float (&r)[R], float &bv, int frozen, float f
             if (!XG) {
                 float xp[R];
                 xcol_lds(w, jn, xp);
-                changed |= coord_update<R, XG>(w, r, bv, u, x);
+                changed |= coord_update(w, r, bv, u, x);
 #pragma unroll
                 for (int k = 0; k < R; ++k) x[k] = xp[k];
             } else {
@@ -590,12 +745,12 @@ LADL_INL float ccd(Wave<R, XG> &w, float (&r)[R], float &bv, int frozen, float f
                     for (int k = 0; k < R; ++k) xc[k] = xn[k];
                 }
                 if (jn >= w.nlds) xcol_ws(w, jn, xn);
-                changed |= coord_update<R, XG>(w, r, bv, u, xc);
+                changed |= coord_update(w, r, bv, u, xc);
             }
             w.c_updates++;
         }
         w.c_sweeps++;
-        float fn = objective<R, XG>(w, r, bv);
+        float fn = objective(w, r, bv);
         bool stop = !changed || (f - fn <= w.opt.tol_f * fn);
         f = fn;
         if (stop) break;
@@ -608,16 +763,15 @@ LADL_INL float ccd(Wave<R, XG> &w, float (&r)[R], float &bv, int frozen, float f
 // --------------------------------------------------------------------------
 
 // ||x_i||_2 of the lane's rows (0 for padding rows)
-template <int R, bool XG>
-LADL_INL void row_norms(const Wave<R, XG> &w, float (&nr)[R])
+template <int R, bool XG, int TW>
+LADL_INL void row_norms(const Wave<R, XG, TW> &w, float (&nr)[R])
 {
-    const int l = lane_id();
 #pragma unroll
     for (int k = 0; k < R; ++k) nr[k] = 0.f;
     for (int j = 0; j < w.p; ++j) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const float x = xget(w, j, 64 * k + l);
+            const float x = xget(w, j, row_of(w, k));
             nr[k] = fmaf(x, x, nr[k]);
         }
     }
@@ -632,12 +786,12 @@ LADL_INL void row_norms(const Wave<R, XG> &w, float (&nr)[R])
 // duplicated row, say) is passed over (modified Gram-Schmidt, basis kept in
 // the A area of LDS).  Writes zs/ss and the per-lane Z bits; returns |S|
 // (= |Z|) or -1.
-template <int R, bool XG>
-LADL_INL int choose_vertex(Wave<R, XG> &w, const float (&r)[R], float bv, uint32_t &zbits)
+template <int R, bool XG, int TW>
+LADL_INL int choose_vertex(Wave<R, XG, TW> &w, const float (&r)[R], float bv, uint32_t &zbits)
 {
     const int l = lane_id(), p = w.p;
     float dist[R];
-    row_norms<R, XG>(w, dist);
+    row_norms(w, dist);
 #pragma unroll
     for (int k = 0; k < R; ++k) dist[k] = (dist[k] > 0.f) ? fabsf(r[k]) / dist[k] : FINF;
     const float dv = (l < p) ? fabsf(bv) : FINF;
@@ -651,7 +805,7 @@ LADL_INL int choose_vertex(Wave<R, XG> &w, const float (&r)[R], float bv, uint32
 #pragma unroll
         for (int k = 0; k < R; ++k)
             if (!((seen >> k) & 1u)) mr = fminf(mr, dist[k]);
-        const float m = wmin(fminf(mr, cseen ? FINF : dv));
+        const float m = tmin(w.tm, fminf(mr, cseen ? FINF : dv));
         if (m == FINF) break;
         const uint64_t cb = ballot(!cseen && l < p && dv == m);
         int row = -1, col = -1;
@@ -662,9 +816,9 @@ LADL_INL int choose_vertex(Wave<R, XG> &w, const float (&r)[R], float bv, uint32
             int best = INT_MAX;
 #pragma unroll
             for (int k = R - 1; k >= 0; --k)
-                if (!((seen >> k) & 1u) && dist[k] == m) best = 64 * k + l;
-            row = wmin_i(best);
-            if (l == (row & 63)) seen |= 1u << (row >> 6);
+                if (!((seen >> k) & 1u) && dist[k] == m) best = row_of(w, k);
+            row = tmin_i(w.tm, best);
+            if (w.wv == row_wave(row, TW) && l == (row & 63)) seen |= 1u << row_slot(row, TW);
         }
         float v = 0.f;
         if (l < p) v = (col >= 0) ? ((l == col) ? 1.f : 0.f) : xget(w, l, row);
@@ -682,7 +836,7 @@ LADL_INL int choose_vertex(Wave<R, XG> &w, const float (&r)[R], float bv, uint32
         if (col >= 0) {
             if (l == col) ctaken = true;
         } else {
-            if (l == (row & 63)) zbits |= 1u << (row >> 6);
+            if (w.wv == row_wave(row, TW) && l == (row & 63)) zbits |= 1u << row_slot(row, TW);
             if (l == 0) w.zs[nz] = row;
             ++nz;
         }
@@ -773,10 +927,10 @@ LADL_INL float lu_solve_t(const float *A, const int *piv, int s, float v)
 }
 
 // Vertex (zs, ss, s): A = X_{Z,S} factored in LDS (A0 keeps it unfactored),
-// b_S = A^{-1} y_Z with up to three refinement steps (residual in fp64), b
-// into vt, residuals into rv (exact zeros on Z), objective into f.
-template <int R, bool XG>
-LADL_INL bool vertex_eval(Wave<R, XG> &w, float (&rv)[R], uint32_t zbits, int s, float &f)
+// b_S = A^{-1} y_Z refined with fp64 residuals, b into vt, residuals into rv
+// (exact zeros on Z), objective into f (and in fp64 into w.fv64).
+template <int R, bool XG, int TW>
+LADL_INL bool vertex_eval(Wave<R, XG, TW> &w, float (&rv)[R], uint32_t zbits, int s, float &f)
 {
     const int l = lane_id(), a0ld = w.a0ld;
     // lane q < s: row Z_q and column S_q, held in registers so that the
@@ -824,19 +978,24 @@ LADL_INL bool vertex_eval(Wave<R, XG> &w, float (&rv)[R], uint32_t zbits, int s,
     // and a row a few ulps of y from its hyperplane must keep its true sign
     double racc[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) racc[k] = (double)w.ys[64 * k + l];
+    for (int k = 0; k < R; ++k) racc[k] = (double)w.ys[row_of(w, k)];
     for (int c = 0; c < s; ++c) {
         const int jc = rdlane(jl, c);
         const double bc = (double)rdlane(xs, c);
 #pragma unroll
-        for (int k = 0; k < R; ++k) racc[k] = fma(-(double)xget(w, jc, 64 * k + l), bc, racc[k]);
+        for (int k = 0; k < R; ++k) racc[k] = fma(-(double)xget(w, jc, row_of(w, k)), bc, racc[k]);
     }
+    double s64 = 0.0;
 #pragma unroll
-    for (int k = 0; k < R; ++k) rv[k] = (float)racc[k];
-#pragma unroll
-    for (int k = 0; k < R; ++k)
-        if ((zbits >> k) & 1u) rv[k] = 0.f;
-    f = objective<R, XG>(w, rv, (l < w.p) ? w.vt[l] : 0.f);
+    for (int k = 0; k < R; ++k) {
+        const bool z = (zbits >> k) & 1u;
+        rv[k] = z ? 0.f : (float)racc[k];
+        s64 += z ? 0.0 : fabs(racc[k]);
+    }
+    const float bl = (l < w.p) ? w.vt[l] : 0.f;
+    s64 += (w.wv == 0) ? (double)w.lam * fabs((double)bl) : 0.0;
+    w.fv64 = tsum_d(w.tm, s64);
+    f = objective(w, rv, bl);
     return true;
 }
 
@@ -844,9 +1003,9 @@ LADL_INL bool vertex_eval(Wave<R, XG> &w, float (&rv)[R], uint32_t zbits, int s,
 // matrix): u_i = sign(r_i) off Z, X_{Z,S}^T u_Z = lambda sign(b_S) -
 // X_{Zc,S}^T u_Zc, c = X^T u.  Lane q returns u_{Z_q} in u, lane j returns
 // c_j in c.
-template <int R, bool XG>
-LADL_INL bool certificate(Wave<R, XG> &w, const float (&rv)[R], uint32_t zbits, int s, float &u, float &c,
-                            bool &unique)
+template <int R, bool XG, int TW>
+LADL_INL bool certificate(Wave<R, XG, TW> &w, const float (&rv)[R], uint32_t zbits, int s, float &u, float &c,
+                          bool &unique)
 {
     const int l = lane_id(), p = w.p, a0ld = w.a0ld;
     const int zl = (l < s) ? w.zs[l] : 0;
@@ -857,10 +1016,11 @@ LADL_INL bool certificate(Wave<R, XG> &w, const float (&rv)[R], uint32_t zbits, 
     for (int j = 0; j < p; ++j) {
         double part = 0.0;
 #pragma unroll
-        for (int k = 0; k < R; ++k) part += (double)(xget(w, j, 64 * k + l) * sgnf(rv[k]));
+        for (int k = 0; k < R; ++k) part += (double)(xget(w, j, row_of(w, k)) * sgnf(rv[k]));
         const double gj = wsum_d(part);
         g = (l == j) ? gj : g;
     }
+    g = tsum_vec_d(w.tm, g);
     if (l < p) w.gd[l] = g;
     __syncthreads();
     uint32_t smask = 0;
@@ -881,10 +1041,15 @@ LADL_INL bool certificate(Wave<R, XG> &w, const float (&rv)[R], uint32_t zbits, 
         if (wmax(fabsf(corr)) <= 1e-7f * fmaxf(1.f, wmax(fabsf(u)))) break;
     }
     double cj = g;
+    float colz = 0.f; // lane j: sum_{i in Z} |x_ij|
     for (int q = 0; q < s; ++q) {
         const float uq = rdlane(u, q);
         const int zq = rdlane(zl, q);
-        if (l < p) cj += (double)xget(w, l, zq) * (double)uq;
+        if (l < p) {
+            const float xv = xget(w, l, zq);
+            cj += (double)xv * (double)uq;
+            colz += fabsf(xv);
+        }
     }
     c = (float)cj;
     const bool offS = (l < p) && !((smask >> l) & 1u);
@@ -893,39 +1058,68 @@ LADL_INL bool certificate(Wave<R, XG> &w, const float (&rv)[R], uint32_t zbits, 
     const float colabs = (l < p) ? w.vca[l] : 0.f;
     const bool viol = offS && (cabs > w.lam * (1.f + TOL_C) + TOL_CA * colabs);
     const bool cert = (umax <= 1.f + TOL_U) && (ballot(viol) == 0);
-    const float mc = wmin(offS ? (w.lam - cabs) / (w.lam + colabs) : FINF);
-    float mr = FINF, nr[R];
-    row_norms<R, XG>(w, nr);
+    const float mc = wmin(offS ? (w.lam - cabs) / (w.lam + colz) : FINF);
+    // rows off Z: |r_i| against |y_i| + sum_{j in S} |x_ij b_j|
+    float sc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) sc[k] = fabsf(w.ys[row_of(w, k)]);
+    for (int q = 0; q < s; ++q) {
+        const int jc = rdlane(jl, q);
+        const float bc = fabsf(w.vt[jc]);
+#pragma unroll
+        for (int k = 0; k < R; ++k) sc[k] = fmaf(fabsf(xget(w, jc, row_of(w, k))), bc, sc[k]);
+    }
+    float mr = FINF;
 #pragma unroll
     for (int k = 0; k < R; ++k)
-        if (!((zbits >> k) & 1u) && nr[k] > 0.f) mr = fminf(mr, fabsf(rv[k]) / nr[k]);
-    mr = wmin(mr);
-    unique = cert && (1.f - umax > MARGIN_U) && (mc > MARGIN_C) && (mr > MARGIN_R * (1.f + w.ynorm1 / w.n));
+        if (!((zbits >> k) & 1u) && row_of(w, k) < w.n)
+            mr = fminf(mr, (sc[k] > 0.f) ? fabsf(rv[k]) / sc[k] : fabsf(rv[k]));
+    mr = tmin(w.tm, mr);
+    unique = cert && (1.f - umax > MARGIN_U) && (mc > MARGIN_C) && (mr > MARGIN_R);
     return cert;
+}
+
+// the Z bits of this wave's rows for the vertex rows zs[0 .. s)
+template <int R, bool XG, int TW>
+LADL_INL uint32_t zbits_of(const Wave<R, XG, TW> &w, int s)
+{
+    const int l = lane_id();
+    const int zn = (l < s) ? w.zs[l] : 0;
+    uint32_t zb = 0;
+    for (int q = 0; q < s; ++q) {
+        const int zq = rdlane(zn, q);
+        if (row_wave(zq, TW) == w.wv && (zq & 63) == l) zb |= 1u << row_slot(zq, TW);
+    }
+    return zb;
 }
 
 // Evaluate the vertex (zs, ss, s) and test its certificate; while it fails,
 // take primal simplex steps along the vertex's edges (a build addition):
-// release the most violated constraint, move to the minimum of f along the
-// edge (again a weighted median) and let the kink reached join the vertex.
+// release a violated constraint, move to the minimum of f along the edge
+// (again a weighted median) and let the kink reached join the vertex.
 // Returns the status; u (lane q) and c (lane j) hold the last dual values.
-template <int R, bool XG>
-LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, float &f, float &u, float &c,
+template <int R, bool XG, int TW>
+LADL_INL int finisher(Wave<R, XG, TW> &w, float (&rv)[R], uint32_t &zbits, int &s, float &f, float &u, float &c,
                       bool &unique, int maxp)
 {
     const int l = lane_id(), p = w.p;
     const float lam = w.lam;
-    float fprev = FINF;
+    double fprev = __builtin_inf();
+    int stalls = 0;
     for (int it = 0;; ++it) {
-        if (!vertex_eval<R, XG>(w, rv, zbits, s, f)) return ST_NOTCERT;
-        if (certificate<R, XG>(w, rv, zbits, s, u, c, unique)) return unique ? ST_CERTIFIED : ST_NONUNIQUE;
+        if (!vertex_eval(w, rv, zbits, s, f)) return ST_NOTCERT;
+        if (certificate(w, rv, zbits, s, u, c, unique)) return unique ? ST_CERTIFIED : ST_NONUNIQUE;
         if (it >= maxp) return ST_MAXITER;
-        // After a step that did not lower f measurably (a degenerate or
-        // nearly degenerate vertex), the released constraint is the violated
-        // one of lowest index (Bland's rule: rows of Z by row index, then
-        // axes), so the steps cannot cycle; otherwise the steepest.
-        const bool bland = !(f < fprev - 1e-7f * fabsf(fprev));
-        fprev = f;
+        // The released constraint is the steepest violated one, except after
+        // a step that did not lower f (compared in fp64: the fp32 values of
+        // neighbouring vertices can tie), where it is the violated one of
+        // lowest index (Bland's rule: rows of Z by row index, then axes);
+        // after STALLS_STICKY such steps Bland's rule, which cannot cycle,
+        // is kept for the rest of the finish.
+        const bool stalled = !(w.fv64 < fprev - 1e-9 * fabs(fprev));
+        stalls += stalled ? 1 : 0;
+        const bool bland = stalled || stalls >= STALLS_STICKY;
+        fprev = w.fv64;
         const int zl = (l < s) ? w.zs[l] : 0;
         const int jl = (l < s) ? w.ss[l] : 0;
         uint32_t smask = 0;
@@ -977,17 +1171,16 @@ LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, f
             const int jc = rdlane(jl, q);
             const float dc = rdlane(dS, q);
 #pragma unroll
-            for (int k = 0; k < R; ++k)
-                xd[k] = fmaf(xget(w, jc, 64 * k + l), dc, xd[k]);
+            for (int k = 0; k < R; ++k) xd[k] = fmaf(xget(w, jc, row_of(w, k)), dc, xd[k]);
         }
         if (!type1) {
 #pragma unroll
-            for (int k = 0; k < R; ++k) xd[k] = fmaf(xget(w, sel, 64 * k + l), dj0, xd[k]);
+            for (int k = 0; k < R; ++k) xd[k] = fmaf(xget(w, sel, row_of(w, k)), dj0, xd[k]);
         }
         const int zsel = type1 ? rdlane(zl, sel) : -1;
 #pragma unroll
         for (int k = 0; k < R; ++k)
-            if ((zbits >> k) & 1u) xd[k] = (64 * k + l == zsel) ? -sgnf(usel) : 0.f;
+            if ((zbits >> k) & 1u) xd[k] = (row_of(w, k) == zsel) ? -sgnf(usel) : 0.f;
         // f(b + t d) = sum |r_i - t xd_i| + lam sum |b_j + t d_j|: kinks at
         // r_i/xd_i (weight |xd_i|) and -b_j/d_j (weight lam |d_j|).  Its
         // right slope at t = 0 is m (1 - |u_i0| or lam - |c_j0|, from the
@@ -1000,20 +1193,20 @@ LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, f
         float a[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            bool pos = rv[k] != 0.f && xd[k] != 0.f &&
-                       __builtin_signbit(rv[k]) == __builtin_signbit(xd[k]);
+            bool pos = rv[k] != 0.f && xd[k] != 0.f && __builtin_signbit(rv[k]) == __builtin_signbit(xd[k]);
             a[k] = pos ? fabsf(rv[k]) / fabsf(xd[k]) : FINF; // weight |xd_i|
         }
-        const bool vpos = (l < p) && lam > 0.f && dl != 0.f && bl != 0.f &&
+        const bool vpos = (w.wv == 0) && (l < p) && lam > 0.f && dl != 0.f && bl != 0.f &&
                           __builtin_signbit(bl) != __builtin_signbit(dl);
         const float av = vpos ? fabsf(bl) / fabsf(dl) : FINF;
         const float wv = vpos ? lam * fabsf(dl) : 0.f;
-        Sel sr = wselect<R, XG>(w, a, xd, av, wv, need, false, -1.f, 0.f);
+        Sel sr = wselect(w, a, xd, av, wv, need, false, -1.f, 0.f);
         if (!(sr.a > 0.f) || sr.a == FINF) return ST_NOTCERT;
+        const int srow = Wave<R, XG, TW>::RT * sr.slot + 64 * sr.wave + sr.lane; // row reached
         // new vertex
         if (type1) {
             if (!sr.virt) {
-                if (l == 0) w.zs[sel] = 64 * sr.slot + sr.lane;
+                if (l == 0) w.zs[sel] = srow;
             } else {
                 if (l == 0) {
                     int c0 = -1;
@@ -1028,7 +1221,7 @@ LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, f
             if (!sr.virt) {
                 if (s >= 32) return ST_NOTCERT;
                 if (l == 0) {
-                    w.zs[s] = 64 * sr.slot + sr.lane;
+                    w.zs[s] = srow;
                     w.ss[s] = sel;
                 }
                 s += 1;
@@ -1040,12 +1233,7 @@ LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, f
             }
         }
         __syncthreads();
-        const int zn = (l < s) ? w.zs[l] : 0;
-        zbits = 0;
-        for (int q = 0; q < s; ++q) {
-            const int zq = rdlane(zn, q);
-            if ((zq & 63) == l) zbits |= 1u << (zq >> 6);
-        }
+        zbits = zbits_of(w, s);
         w.c_pivots++;
     }
     return ST_MAXITER;
@@ -1054,52 +1242,63 @@ LADL_INL int finisher(Wave<R, XG> &w, float (&rv)[R], uint32_t &zbits, int &s, f
 // Degenerate vertices (more rows on their hyperplanes than active axes,
 // e.g. duplicated rows) can make the edge steps cycle; a tiny deterministic
 // perturbation of y separates such rows.
-template <int R, bool XG>
-LADL_INL void perturb_y(Wave<R, XG> &w)
+template <int R, bool XG, int TW>
+LADL_INL void perturb_y(Wave<R, XG, TW> &w)
 {
-    const int l = lane_id();
     const float ybar = w.ynorm1 / (float)w.n;
-    for (int i = l; i < w.n; i += 64) w.ys[i] += PERTURB_REL * (fabsf(w.ys[i]) + ybar) * perturb_dir(i);
+    for (int i = w.rb; i < w.n; i += Wave<R, XG, TW>::RT)
+        w.ys[i] += PERTURB_REL * (fabsf(w.ys[i]) + ybar) * perturb_dir(i);
     ws_sync<XG>();
 }
 
-// objective of b (in bvec) recomputed with fp64 residuals and sums
-template <int R, bool XG>
-LADL_INL float objective64(Wave<R, XG> &w, float bval)
+// y back from HBM (after a perturbation)
+template <int R, bool XG, int TW>
+LADL_INL void restore_y(Wave<R, XG, TW> &w, const float *yg)
+{
+    for (int i = w.rb; i < w.n; i += Wave<R, XG, TW>::RT) w.ys[i] = yg[i];
+    ws_sync<XG>();
+}
+
+// objective of b (one coefficient per lane) recomputed with fp64 residuals
+// and sums
+template <int R, bool XG, int TW>
+LADL_INL float objective64(Wave<R, XG, TW> &w, float bval)
 {
     const int l = lane_id();
     double acc[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) acc[k] = (k < w.nslot) ? (double)w.ys[64 * k + l] : 0.0;
+    for (int k = 0; k < R; ++k) acc[k] = (k < w.nslot) ? (double)w.ys[row_of(w, k)] : 0.0;
     for (int j = 0; j < w.p; ++j) {
         double bj = (double)rdlane(bval, j);
         if (bj != 0.0) {
 #pragma unroll
             for (int k = 0; k < R; ++k)
-                if (k < w.nslot) acc[k] -= (double)xget(w, j, 64 * k + l) * bj;
+                if (k < w.nslot) acc[k] -= (double)xget(w, j, row_of(w, k)) * bj;
         }
     }
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < R; ++k) s += fabs(acc[k]);
-    s += (l < w.p) ? (double)w.lam * fabs((double)bval) : 0.0;
-    return (float)wsum_d(s);
+    s += (w.wv == 0 && l < w.p) ? (double)w.lam * fabs((double)bval) : 0.0;
+    return (float)tsum_d(w.tm, s);
 }
 
 // --------------------------------------------------------------------------
 // one solve (all its path steps)
 // --------------------------------------------------------------------------
-template <int R, bool XG>
-LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
+template <int R, bool XG, int TW>
+LADL_INL void solve_item(Wave<R, XG, TW> &w, const SolveArgs &a, int s)
 {
+    constexpr int RT = Wave<R, XG, TW>::RT;
     const int l = lane_id();
     const int k = a.problem ? a.problem[s] : s;
     const int64_t r0 = a.row_off[k];
     w.n = (int)(a.row_off[k + 1] - r0);
     w.p = a.p_arr[k];
-    w.nslot = (w.n + 63) >> 6;
+    w.nslot = (w.n + RT - 1) / RT;
     const int p = w.p;
-    const bool finite = load_problem<R, XG>(w, a.X + a.x_off[k], a.y + r0);
+    const bool lead = (w.wv == 0); // the wave that writes the outputs
+    const bool finite = load_problem(w, a.X + a.x_off[k], a.y + r0);
     const int64_t bbase = (int64_t)a.path_len * a.b_off[s];
     // starting point
     float b0 = 0.f;
@@ -1125,8 +1324,8 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
             fout = __builtin_nanf("");
         } else {
             w.lam = fmaxf(lam_in, w.opt.lambda_min);
-            residuals<R, XG>(w, r, bv);
-            float f = objective<R, XG>(w, r, bv);
+            residuals(w, r, bv);
+            float f = objective(w, r, bv);
             status = ST_NOTCERT;
             bool done = false, unique = false, have_vertex = false;
             uint32_t zbits = 0;
@@ -1141,15 +1340,15 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
             int frozen = -1, round = 0, kax = 0;
             float fbest = FINF;
             for (;;) {
-                f = ccd<R, XG>(w, r, bv, frozen, f); // the only CCD call site
+                f = ccd(w, r, bv, frozen, f); // the only CCD call site
                 float sprobe = 0.f;
                 bool more;
                 if (phase == 0) {
                     if (snap) {
-                        vs = choose_vertex<R, XG>(w, r, bv, zbits);
+                        vs = choose_vertex(w, r, bv, zbits);
                         have_vertex = vs >= 0;
                         if (have_vertex) {
-                            int st = finisher<R, XG>(w, rv, zbits, vs, fv, u, c, unique, 0);
+                            int st = finisher(w, rv, zbits, vs, fv, u, c, unique, 0);
                             if (st == ST_CERTIFIED || st == ST_NONUNIQUE) {
                                 status = st;
                                 done = true;
@@ -1190,10 +1389,10 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
                     const float d = sprobe - rdlane(bv, kax);
                     if (d != 0.f) {
 #pragma unroll
-                        for (int kk = 0; kk < R; ++kk) r[kk] = fmaf(-xget(w, kax, 64 * kk + l), d, r[kk]);
+                        for (int kk = 0; kk < R; ++kk) r[kk] = fmaf(-xget(w, kax, row_of(w, kk)), d, r[kk]);
                     }
                     bv = (l == kax) ? sprobe : bv;
-                    f = objective<R, XG>(w, r, bv);
+                    f = objective(w, r, bv);
                     frozen = kax;
                     phase = 1;
                 } else {
@@ -1207,10 +1406,10 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
                 bool perturbed = false;
                 for (int attempt = 0; attempt < 2 && !done; ++attempt) {
                     if (attempt == 1) {
-                        perturb_y<R, XG>(w);
+                        perturb_y(w);
                         perturbed = true;
                     }
-                    status = finisher<R, XG>(w, rv, zbits, vs, fv, u, c, unique, maxp);
+                    status = finisher(w, rv, zbits, vs, fv, u, c, unique, maxp);
                     done = (status == ST_CERTIFIED || status == ST_NONUNIQUE);
                 }
                 if (done && perturbed) {
@@ -1221,26 +1420,22 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
                     float sg[R];
 #pragma unroll
                     for (int kk = 0; kk < R; ++kk) sg[kk] = sgnf(rv[kk]);
-                    const float *yg = a.y + r0;
-                    for (int i = l; i < w.n; i += 64) w.ys[i] = yg[i];
-                    ws_sync<XG>();
+                    restore_y(w, a.y + r0);
                     double yu = 0.0;
 #pragma unroll
                     for (int kk = 0; kk < R; ++kk)
-                        if (kk < w.nslot) yu += (double)w.ys[64 * kk + l] * (double)sg[kk];
-                    if (l < vs) yu += (double)w.ys[w.zs[l]] * (double)u;
-                    yu = wsum_d(yu);
-                    done = vertex_eval<R, XG>(w, rv, zbits, vs, fv);
+                        if (kk < w.nslot) yu += (double)w.ys[row_of(w, kk)] * (double)sg[kk];
+                    if (lead && l < vs) yu += (double)w.ys[w.zs[l]] * (double)u;
+                    yu = tsum_d(w.tm, yu);
+                    done = vertex_eval(w, rv, zbits, vs, fv);
                     if (done) {
-                        float fo = objective64<R, XG>(w, (l < p) ? w.vt[l] : 0.f);
+                        float fo = objective64(w, (l < p) ? w.vt[l] : 0.f);
                         done = (double)fo - yu <= 2e-6 * fmax(1.0, (double)fo);
                     }
                     status = done ? ST_NONUNIQUE : ST_NOTCERT;
                 } else if (perturbed) {
                     // failed even when perturbed: put y back for the next path step
-                    const float *yg = a.y + r0;
-                    for (int i = l; i < w.n; i += 64) w.ys[i] = yg[i];
-                    ws_sync<XG>();
+                    restore_y(w, a.y + r0);
                 }
             }
             if (done) {
@@ -1249,28 +1444,28 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
             } else if (!snap) {
                 status = ST_MAXITER;
             }
-            fout = objective64<R, XG>(w, bv);
+            fout = objective64(w, bv);
         }
-        // outputs
-        if (l < p) bout[l] = bv;
+        // outputs (first wave of the team)
         uint64_t act = ballot(l < p && bv != 0.f);
-        if (l == 0) {
-            a.obj_out[o] = fout;
-            a.active_out[o] = (uint32_t)act;
-            a.status_out[o] = status;
-            if (a.iters_out) {
-                a.iters_out[4 * o + 0] = w.c_sweeps;
-                a.iters_out[4 * o + 1] = w.c_updates;
-                a.iters_out[4 * o + 2] = w.c_probes;
-                a.iters_out[4 * o + 3] = w.c_pivots;
+        if (lead) {
+            if (l < p) bout[l] = bv;
+            if (l == 0) {
+                a.obj_out[o] = fout;
+                a.active_out[o] = (uint32_t)act;
+                a.status_out[o] = status;
+                if (a.iters_out) {
+                    a.iters_out[4 * o + 0] = w.c_sweeps;
+                    a.iters_out[4 * o + 1] = w.c_updates;
+                    a.iters_out[4 * o + 2] = w.c_probes;
+                    a.iters_out[4 * o + 3] = w.c_pivots;
+                }
             }
-        }
-        {
             // Z rows in ascending order, -1 padded
             const bool zr = zcount > 0 && l < zcount;
             const int zl = zr ? w.zs[l] : INT_MAX;
             int rank = 0;
-            for (int q = 0; q < zcount; ++q) rank += (rdlane(zl, q) < zl) ? 1 : 0;
+            for (int qq = 0; qq < zcount; ++qq) rank += (rdlane(zl, qq) < zl) ? 1 : 0;
             if (zr)
                 a.zrows_out[(int64_t)ZPAD * o + rank] = zl;
             else if (l < ZPAD)
@@ -1298,7 +1493,8 @@ LADL_INL void solve_item(Wave<R, XG> &w, const SolveArgs &a, int s)
 // take 0.90 instead of 1.21 s.  R = 8 (170 VGPRs, 2 waves) is compiled for
 // 3 (168 VGPRs, no spill in the update loop): 6144 problems of n in
 // (256, 512] 0.315 -> 0.301 s.  R = 16 at 3 waves spills in the update loop
-// and ran 16% slower, so it keeps the compiler's 2.
+// and ran 16% slower, so it keeps the compiler's 2.  The team kernels take
+// the budget of their per-wave R.
 constexpr int DENSE_WAVES_PER_SIMD = 4;
 constexpr int R32_WAVES_PER_SIMD = 2;
 constexpr int R8_WAVES_PER_SIMD = 3;
@@ -1307,21 +1503,30 @@ __host__ __device__ constexpr int waves_per_eu(int R, bool dense)
     return dense ? DENSE_WAVES_PER_SIMD : (R >= 32 ? R32_WAVES_PER_SIMD : (R == 8 ? R8_WAVES_PER_SIMD : 1));
 }
 
-template <int R, bool XG, bool DENSE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R, DENSE))))
+template <int R, bool XG, bool DENSE, int TW>
+__global__ __launch_bounds__(64 * TW) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R, DENSE))))
 void k_wave(SolveArgs a)
 {
     extern __shared__ float smem[];
-    Wave<R, XG> w;
-    carve<R, XG>(w, smem, a.pmax, a.nlds, XG ? a.gws + (int64_t)blockIdx.x * a.gws_stride : nullptr);
+    Wave<R, XG, TW> w;
+    const int wv = (TW > 1) ? (int)(threadIdx.x >> 6) : 0;
+    carve(w, smem, a.pmax, a.nlds, XG ? a.gws + (int64_t)blockIdx.x * a.gws_stride : nullptr, wv);
     w.opt = a.opt;
     const int l = lane_id();
     for (;;) {
         int q = 0;
-        if (l == 0) q = atomicAdd(a.counter, 1);
-        q = rdlane(q, 0);
+        if constexpr (TW == 1) {
+            if (l == 0) q = atomicAdd(a.counter, 1);
+            q = rdlane(q, 0);
+        } else {
+            // the team's next solve, broadcast through LDS (the solve's own
+            // barriers separate this read from the next write)
+            if (wv == 0 && l == 0) w.qw[0] = atomicAdd(a.counter, 1);
+            __syncthreads();
+            q = uni(w.qw[0]);
+        }
         if (q >= a.num_items) break;
-        solve_item<R, XG>(w, a, a.order[q]);
+        solve_item(w, a, a.order[q]);
     }
 }
 
@@ -1331,8 +1536,11 @@ __global__ void k_reset(int32_t *c, int n)
     if (i < n) c[i] = 0;
 }
 
-size_t wave_lds_bytes(int R, int pmax, bool xg, int nlds) { return 4 * wave_lds_floats(R, pmax, xg, nlds); }
-size_t wave_ws_floats_host(int R, int pmax, int nlds) { return wave_ws_floats(R, pmax, nlds); }
+size_t wave_lds_bytes(int R, int pmax, bool xg, int nlds, int tw)
+{
+    return 4 * wave_lds_floats(R, pmax, xg, nlds, tw) + 16;
+}
+size_t wave_ws_floats_host(int R, int pmax, int nlds, int tw) { return wave_ws_floats(R, pmax, nlds, tw); }
 
 hipError_t launch_reset(int32_t *counters, int n, hipStream_t s)
 {
@@ -1340,104 +1548,121 @@ hipError_t launch_reset(int32_t *counters, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int R, bool XG, bool DENSE>
+template <int R, bool XG, bool DENSE, int TW>
 static hipError_t launch_wave_t(const SolveArgs &a, int grid, hipStream_t s)
 {
-    size_t lds = wave_lds_bytes(R, a.pmax, XG, a.nlds);
+    size_t lds = wave_lds_bytes(R, a.pmax, XG, a.nlds, TW);
     static bool attr = false;
     if (!attr) {
         // allow dynamic LDS beyond the default limit; harmless if refused
-        (void)hipFuncSetAttribute((const void *)k_wave<R, XG, DENSE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
+        (void)hipFuncSetAttribute((const void *)k_wave<R, XG, DENSE, TW>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((k_wave<R, XG, DENSE>), dim3(grid), dim3(64), lds, s, a);
+    hipLaunchKernelGGL((k_wave<R, XG, DENSE, TW>), dim3(grid), dim3(64 * TW), lds, s, a);
     return hipGetLastError();
 }
 
-template <int R, bool XG, bool DENSE>
+template <int R, bool XG, bool DENSE, int TW>
 static int max_blocks_t(int pmax, int nlds)
 {
     int nb = 0;
-    size_t lds = wave_lds_bytes(R, pmax, XG, nlds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_wave<R, XG, DENSE>, 64, lds) != hipSuccess) return 0;
+    size_t lds = wave_lds_bytes(R, pmax, XG, nlds, TW);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_wave<R, XG, DENSE, TW>, 64 * TW, lds) != hipSuccess)
+        return 0;
     return nb;
 }
 
 bool wave_has_dense(int R) { return R == 1 || R == 2 || R == 4; }
 
+// team sizes built for rows-per-lane bucket Rt (R = Rt / tw rows per lane
+// of each wave): tw = 1 always; tw = 2, 4 for the n > 1024 bucket (Rt = 32)
+bool wave_has_team(int Rt, int tw) { return tw == 1 || (Rt == 32 && (tw == 2 || tw == 4)); }
+
 // the variants that exist: R in {1,2,4,8,16} with X in LDS or HBM, R = 32
-// with X in HBM, and the dense register budget for R <= 4 with X in HBM
-hipError_t launch_wave(int R, bool xg, bool dense, const SolveArgs &a, int grid, hipStream_t s)
+// with X in HBM, the dense register budget for R <= 4 with X in HBM, and the
+// teams of the n > 1024 bucket (2 x 16, 4 x 8 rows per lane) with X in HBM
+hipError_t launch_wave(int Rt, bool xg, bool dense, int tw, const SolveArgs &a, int grid, hipStream_t s)
 {
+    if (tw == 2 || tw == 4) {
+        if (!xg || dense || Rt != 32) return hipErrorInvalidValue;
+        return tw == 2 ? launch_wave_t<16, true, false, 2>(a, grid, s) : launch_wave_t<8, true, false, 4>(a, grid, s);
+    }
+    if (tw != 1) return hipErrorInvalidValue;
     if (dense) {
         if (!xg) return hipErrorInvalidValue;
-        switch (R) {
-        case 1: return launch_wave_t<1, true, true>(a, grid, s);
-        case 2: return launch_wave_t<2, true, true>(a, grid, s);
-        case 4: return launch_wave_t<4, true, true>(a, grid, s);
+        switch (Rt) {
+        case 1: return launch_wave_t<1, true, true, 1>(a, grid, s);
+        case 2: return launch_wave_t<2, true, true, 1>(a, grid, s);
+        case 4: return launch_wave_t<4, true, true, 1>(a, grid, s);
         default: return hipErrorInvalidValue;
         }
     }
     if (xg) {
-        switch (R) {
-        case 1: return launch_wave_t<1, true, false>(a, grid, s);
-        case 2: return launch_wave_t<2, true, false>(a, grid, s);
-        case 4: return launch_wave_t<4, true, false>(a, grid, s);
-        case 8: return launch_wave_t<8, true, false>(a, grid, s);
-        case 16: return launch_wave_t<16, true, false>(a, grid, s);
-        case 32: return launch_wave_t<32, true, false>(a, grid, s);
+        switch (Rt) {
+        case 1: return launch_wave_t<1, true, false, 1>(a, grid, s);
+        case 2: return launch_wave_t<2, true, false, 1>(a, grid, s);
+        case 4: return launch_wave_t<4, true, false, 1>(a, grid, s);
+        case 8: return launch_wave_t<8, true, false, 1>(a, grid, s);
+        case 16: return launch_wave_t<16, true, false, 1>(a, grid, s);
+        case 32: return launch_wave_t<32, true, false, 1>(a, grid, s);
         default: return hipErrorInvalidValue;
         }
     }
-    switch (R) {
-    case 1: return launch_wave_t<1, false, false>(a, grid, s);
-    case 2: return launch_wave_t<2, false, false>(a, grid, s);
-    case 4: return launch_wave_t<4, false, false>(a, grid, s);
-    case 8: return launch_wave_t<8, false, false>(a, grid, s);
-    case 16: return launch_wave_t<16, false, false>(a, grid, s);
+    switch (Rt) {
+    case 1: return launch_wave_t<1, false, false, 1>(a, grid, s);
+    case 2: return launch_wave_t<2, false, false, 1>(a, grid, s);
+    case 4: return launch_wave_t<4, false, false, 1>(a, grid, s);
+    case 8: return launch_wave_t<8, false, false, 1>(a, grid, s);
+    case 16: return launch_wave_t<16, false, false, 1>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-int wave_max_blocks_per_cu(int R, int pmax, bool xg, bool dense, int nlds)
+int wave_max_blocks_per_cu(int Rt, int pmax, bool xg, bool dense, int tw, int nlds)
 {
+    if (tw == 2 || tw == 4) {
+        if (!xg || dense || Rt != 32) return 0;
+        return tw == 2 ? max_blocks_t<16, true, false, 2>(pmax, nlds) : max_blocks_t<8, true, false, 4>(pmax, nlds);
+    }
+    if (tw != 1) return 0;
     if (dense) {
         if (!xg) return 0;
-        switch (R) {
-        case 1: return max_blocks_t<1, true, true>(pmax, nlds);
-        case 2: return max_blocks_t<2, true, true>(pmax, nlds);
-        case 4: return max_blocks_t<4, true, true>(pmax, nlds);
+        switch (Rt) {
+        case 1: return max_blocks_t<1, true, true, 1>(pmax, nlds);
+        case 2: return max_blocks_t<2, true, true, 1>(pmax, nlds);
+        case 4: return max_blocks_t<4, true, true, 1>(pmax, nlds);
         default: return 0;
         }
     }
     if (xg) {
-        switch (R) {
-        case 1: return max_blocks_t<1, true, false>(pmax, nlds);
-        case 2: return max_blocks_t<2, true, false>(pmax, nlds);
-        case 4: return max_blocks_t<4, true, false>(pmax, nlds);
-        case 8: return max_blocks_t<8, true, false>(pmax, nlds);
-        case 16: return max_blocks_t<16, true, false>(pmax, nlds);
-        case 32: return max_blocks_t<32, true, false>(pmax, nlds);
+        switch (Rt) {
+        case 1: return max_blocks_t<1, true, false, 1>(pmax, nlds);
+        case 2: return max_blocks_t<2, true, false, 1>(pmax, nlds);
+        case 4: return max_blocks_t<4, true, false, 1>(pmax, nlds);
+        case 8: return max_blocks_t<8, true, false, 1>(pmax, nlds);
+        case 16: return max_blocks_t<16, true, false, 1>(pmax, nlds);
+        case 32: return max_blocks_t<32, true, false, 1>(pmax, nlds);
         default: return 0;
         }
     }
-    switch (R) {
-    case 1: return max_blocks_t<1, false, false>(pmax, nlds);
-    case 2: return max_blocks_t<2, false, false>(pmax, nlds);
-    case 4: return max_blocks_t<4, false, false>(pmax, nlds);
-    case 8: return max_blocks_t<8, false, false>(pmax, nlds);
-    case 16: return max_blocks_t<16, false, false>(pmax, nlds);
+    switch (Rt) {
+    case 1: return max_blocks_t<1, false, false, 1>(pmax, nlds);
+    case 2: return max_blocks_t<2, false, false, 1>(pmax, nlds);
+    case 4: return max_blocks_t<4, false, false, 1>(pmax, nlds);
+    case 8: return max_blocks_t<8, false, false, 1>(pmax, nlds);
+    case 16: return max_blocks_t<16, false, false, 1>(pmax, nlds);
     default: return 0;
     }
 }
-
 
 // --------------------------------------------------------------------------
 // H10: gradient through the optimal vertex.  At a certified vertex b_S =
 // X_{Z,S}^{-1} y_Z (the vertex form of Section 3.2), so for a loss L with
 // g = dL/db:  w = X_{Z,S}^{-T} g_S,  dL/dy_Z = w,  dL/dX_{Z,S} = -w b_S^T,
-// and every other entry of dL/dy and dL/dX is zero.
+// and every other entry of dL/dy and dL/dX is zero.  At a NONUNIQUE output
+// (certified, but a margin at fp32 resolution) this is the derivative of the
+// returned vertex, one of the one-sided derivatives of the solution map.
 // Two launches: k_bw_vertex runs the dense zero fill (blocks below
 // fill_blocks, grid-stride, HBM-bound) side by side with the per-solve
 // vertex solves (one wave each, latency-bound), which leave w in a small
@@ -1470,7 +1695,7 @@ __device__ __forceinline__ bool bw_vertex(const BackwardArgs &a, int s, BwVertex
     v.ns = popc64(sb);
     v.zl = (l < ZPAD) ? a.zrows[(int64_t)ZPAD * o + l] : -1;
     const int nz = popc64(ballot(l < ZPAD && v.zl >= 0));
-    bool ok = (status == ST_CERTIFIED) && v.ns == nz && v.ns > 0;
+    bool ok = (status == ST_CERTIFIED || status == ST_NONUNIQUE) && v.ns == nz && v.ns > 0;
     if (ok && l < v.ns && (v.zl < 0 || v.zl >= v.n)) ok = false;
     ok = ballot(!ok) == 0;
     // the c-th set bit of the S mask, for lane c

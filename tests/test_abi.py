@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 import paper_2510_15649_amd as L
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -61,3 +63,21 @@ def test_no_packed_fp32_or_scalar_stores_in_device_code():
             asm = open(out).read()
         assert "v_pk_fma_f32" not in asm and "v_pk_add_f32" not in asm and "v_pk_mul_f32" not in asm, name
         assert not re.search(r"\bs_(store|atomic|buffer_store|dcache_wb)", asm), name
+
+
+def test_binding_rejects_bad_tensors():
+    """The binding checks dtype, device, contiguity and size before any
+    pointer reaches the C ABI (CPU tensors are rejected before the library
+    is asked for anything device-side)."""
+    import torch
+    from paper_2510_15649_amd import _check
+    t = torch.zeros(8, dtype=torch.float32)
+    with pytest.raises(ValueError, match="device tensor"):
+        _check(t, "X", "f32", 8)
+    with pytest.raises(ValueError, match="float32"):
+        _check(t.double(), "X", "f32", 8)
+    with pytest.raises(ValueError, match="int32"):
+        _check(t, "status", "i32", 8)
+    with pytest.raises(ValueError, match="required"):
+        _check(None, "X", "f32", 8)
+    _check(None, "b_init", "f32", 8, optional=True)

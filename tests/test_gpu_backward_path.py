@@ -6,7 +6,7 @@ import pytest
 import oracle as O
 import paper_2510_15649_amd as L
 from paper_2510_15649_amd import workloads as W
-from parity import MARGIN_R, MARGIN_UC, compare, oracle_ref, to_numpy
+from parity import compare, gradient_error, oracle_ref, strict_unique, to_numpy
 
 pytestmark = pytest.mark.gpu
 
@@ -30,6 +30,11 @@ def solve_and_backward(torch, w, grad, step=None, **opts):
 
 
 def check_backward(w, gpu, gy, gX, ref, grad, step, min_checked):
+    """Every output's gradient block: zero without a certificate; at an
+    optimum the oracle certifies unique with fp32-resolvable margins, the
+    oracle's vertex-form gradient (and the GPU must have certified it);
+    elsewhere (certified, not strictly unique) the vertex-form gradient at
+    the GPU's own vertex.  Returns the number checked against the oracle."""
     Lp = w.path_len
     checked = 0
     for s in range(w.num_solves):
@@ -39,22 +44,27 @@ def check_backward(w, gpu, gy, gX, ref, grad, step, min_checked):
         xo, ro = int(w.x_off[k]), int(w.row_off[k])
         gyk = gy[ro:ro + n]
         gXk = gX[xo:xo + n * p].reshape(n, p)
-        if gpu["status"][o] != L.CERTIFIED:
+        st = int(gpu["status"][o])
+        if st not in (L.CERTIFIED, L.NONUNIQUE):
             assert np.all(gyk == 0) and np.all(gXk == 0)
             continue
-        mu, mr = ref["margin"][o]
-        if not (ref["cert"][o] == 2 and mu >= MARGIN_UC and mr >= MARGIN_R):
-            continue
         Xk, yk = w.block(k)
-        bo = Lp * int(ref["b_off"][s]) + step * p
-        bref = ref["b"][bo:bo + p]
-        Z = [z for z in ref["zrows"][o] if z >= 0]
         goff = int(ref["b_off"][s])
-        dy, dX = O.backward(Xk, yk, float(w.lam[o]), bref, Z, grad[goff:goff + p].astype(np.float64))
-        scale = 1.0 + np.max(np.abs(dX))
-        assert np.max(np.abs(gyk - dy)) <= 1e-4 * (1 + np.max(np.abs(dy))), (s, gyk[gyk != 0], dy[dy != 0])
-        assert np.max(np.abs(gXk - dX)) <= 1e-4 * scale, s
-        checked += 1
+        gk = grad[goff:goff + p]
+        if strict_unique(ref, o):
+            assert st == L.CERTIFIED, (s, st)
+            bo = Lp * int(ref["b_off"][s]) + step * p
+            bref = ref["b"][bo:bo + p]
+            Z = [z for z in ref["zrows"][o] if z >= 0]
+            err = gradient_error(Xk, yk, w.lam[o], bref, Z, gk, gyk, gXk)
+            assert err <= 1e-4, (s, err)
+            checked += 1
+        else:
+            bo = Lp * goff + step * p
+            bg = gpu["b"][bo:bo + p]
+            zg = gpu["zero_rows"][32 * o:32 * o + 32]
+            err = gradient_error(Xk, yk, w.lam[o], bg, zg[zg >= 0], gk, gyk, gXk)
+            assert err <= 1e-4, (s, st, err)
     assert checked >= min_checked, checked
     return checked
 
@@ -65,7 +75,7 @@ def test_backward_c3_vs_closed_form(torch):
     ref = oracle_ref(w)
     fails, st = compare(w, g, ref)
     assert not fails, fails[:3]
-    n = check_backward(w, g, gy, gX, ref, w.grad_b, 0, min_checked=100)
+    n = check_backward(w, g, gy, gX, ref, w.grad_b, 0, min_checked=120)
     print("checked", n, flush=True)
 
 
@@ -79,7 +89,7 @@ def test_backward_vs_finite_differences(torch):
     h = 1e-6
     checked = 0
     for s in range(w.num_solves):
-        if g["status"][s] != L.CERTIFIED:
+        if g["status"][s] not in (L.CERTIFIED, L.NONUNIQUE):
             continue
         k = s
         Xk, yk = w.block(k)

@@ -8,7 +8,7 @@ import pytest
 import oracle as O
 import paper_2510_15649_amd as L
 from paper_2510_15649_amd import workloads as W
-from parity import MARGIN_R, MARGIN_UC, compare, f64, oracle_ref, to_numpy
+from parity import compare, f64, gradient_error, oracle_ref, strict_unique, to_numpy
 
 pytestmark = pytest.mark.gpu
 
@@ -35,6 +35,8 @@ def check_every_output(w, g, max_flagged=0):
     objective is finite and non-negative; the S mask is the support of b."""
     st = g["status"]
     bad = np.flatnonzero(~np.isin(st, OK))
+    print(f"statuses {np.bincount(st, minlength=6).tolist()}; flagged outputs (solve, step): "
+          f"{[divmod(int(o), w.path_len) for o in bad[:8]]}", flush=True)
     assert len(bad) <= max_flagged, (len(bad), np.bincount(st, minlength=6))
     assert np.all(st[bad] == L.NOTCERTIFIED)
     assert np.all(np.isfinite(g["obj"])) and np.all(g["obj"] >= 0)
@@ -91,20 +93,19 @@ def test_c3_full_forward_and_backward_sampled(torch):
         n, p = w.n(k), int(w.p[k])
         xo, ro = int(w.x_off[k]), int(w.row_off[k])
         gyk, gXk = gy[ro:ro + n], gX[xo:xo + n * p].reshape(n, p)
-        if g["status"][s] != L.CERTIFIED:
+        if g["status"][s] not in OK:
             assert np.all(gyk == 0) and np.all(gXk == 0)
             continue
-        mu, mr = ref["margin"][idx]
-        if not (ref["cert"][idx] == 2 and mu >= MARGIN_UC and mr >= MARGIN_R):
+        if not strict_unique(ref, idx):
             continue
+        assert g["status"][s] == L.CERTIFIED, s
         Xk, yk = w.block(k)
         bref = ref["b"][int(ref["b_off"][idx]):int(ref["b_off"][idx]) + p]
         Z = [z for z in ref["zrows"][idx] if z >= 0]
-        dy, dX = O.backward(Xk, yk, float(w.lam[s]), bref, Z, w.grad_b[off[s]:off[s] + p].astype(np.float64))
-        assert np.max(np.abs(gyk - dy)) <= 1e-4 * (1 + np.max(np.abs(dy))), s
-        assert np.max(np.abs(gXk - dX)) <= 1e-4 * (1 + np.max(np.abs(dX))), s
+        err = gradient_error(Xk, yk, w.lam[s], bref, Z, w.grad_b[off[s]:off[s] + p], gyk, gXk)
+        assert err <= 1e-4, (s, err)
         checked += 1
-    assert checked >= 32, checked
+    assert checked >= 60, checked
 
 
 def test_c4_full_path_sampled(torch):
@@ -114,7 +115,9 @@ def test_c4_full_path_sampled(torch):
     and consistency; 24 seeded problems of at most 400 rows and 12 features
     (the oracle's cost grows steeply with n and p) are compared with the
     oracle along their whole path, and their gradient blocks with the
-    oracle's vertex-form gradient."""
+    oracle's vertex-form gradient.  The sample holds 24 problems drawn
+    uniformly and 16 drawn from those with n > 1024 and p > 24 (the
+    largest bucket, run by its own kernel instance)."""
     w = W.config4()
     print(f"[gpu] full c4 problems={w.num_problems} path={w.path_len}", flush=True)
     plan = L.Plan.for_workload(w)
@@ -129,8 +132,9 @@ def test_c4_full_path_sampled(torch):
     check_every_output(w, g, max_flagged=2)
     Lp = w.path_len
     ns = np.diff(w.row_off)
-    small = np.flatnonzero((ns <= 400) & (w.p <= 12))
-    ids = np.sort(np.random.default_rng(23).choice(small, size=24, replace=False))
+    rng = np.random.default_rng(23)
+    big = np.flatnonzero((ns > 1024) & (w.p > 24))
+    ids = np.union1d(rng.choice(w.num_problems, size=24, replace=False), rng.choice(big, size=16, replace=False))
     ws = W.config4(problems=ids)
     off_full, off_s = b_offsets(w), b_offsets(ws)
     gs = {"b": np.zeros(int(w.p[ids].sum()) * Lp, np.float32), "obj": g["obj"].reshape(-1, Lp)[ids].ravel(),
@@ -154,21 +158,20 @@ def test_c4_full_path_sampled(torch):
         xo, ro = int(w.x_off[k]), int(w.row_off[k])
         gyk = gy_d[ro:ro + n].cpu().numpy()
         gXk = gX_d[xo:xo + n * p].cpu().numpy().reshape(n, p)
-        if g["status"][o] != L.CERTIFIED:
+        if g["status"][o] not in OK:
             assert np.all(gyk == 0) and np.all(gXk == 0)
             continue
         ro_ = j * Lp + t
-        mu, mr = ref["margin"][ro_]
-        if not (ref["cert"][ro_] == 2 and mu >= MARGIN_UC and mr >= MARGIN_R):
+        if not strict_unique(ref, ro_):
             continue
+        assert g["status"][o] == L.CERTIFIED, k
         Xk, yk = w.block(k)
         bref = ref["b"][Lp * int(ref["b_off"][j]) + t * p: Lp * int(ref["b_off"][j]) + t * p + p]
         Z = [z for z in ref["zrows"][ro_] if z >= 0]
-        dy, dX = O.backward(Xk, yk, float(w.lam[o]), bref, Z, w.grad_b[off_full[k]:off_full[k] + p].astype(np.float64))
-        assert np.max(np.abs(gyk - dy)) <= 1e-4 * (1 + np.max(np.abs(dy))), k
-        assert np.max(np.abs(gXk - dX)) <= 1e-4 * (1 + np.max(np.abs(dX))), k
+        err = gradient_error(Xk, yk, w.lam[o], bref, Z, w.grad_b[off_full[k]:off_full[k] + p], gyk, gXk)
+        assert err <= 1e-4, (k, err)
         checked += 1
-    assert checked >= 8, checked
+    assert checked >= 30, checked
     # the fp64 objective of a sample of outputs of every size matches the reported one
     rng = np.random.default_rng(24)
     for o in rng.choice(w.num_solves * Lp, size=256, replace=False):
