@@ -369,6 +369,38 @@ int ladl_cv_destroy(ladl_cv_t cv);
 int ladl_cv_run(ladl_cv_t cv, const float *X, const float *y, const float *lambda, float *fold_error,
                 float *cv_error, int32_t *best, int32_t *fold_status, void *stream);
 
+/*
+ * Allocation-free forward solve, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same solve, kernels and outputs as
+ * ladl_solve_f32 on a uniform batch, without a plan: num_problems problems
+ * of n rows and p features each, packed back to back (problem k's
+ * row-major X block at X + k*n*p, its y at y + k*n), solve k runs problem
+ * k along its lambda path lambda[k*path_len .. (k+1)*path_len), and the
+ * outputs are laid out as ladl_solve_f32 lays them out (b of (k, t) at
+ * b + (k*path_len + t)*p).  opt may be NULL (defaults); its schedule field
+ * is ignored: X is always held in LDS.
+ *
+ * Nothing is allocated and no library routine that allocates is called:
+ * the work-queue counter and the per-problem metadata live in a fixed
+ * device array of about 2.1 MB, one per GPU, held by the library until the
+ * process ends, and rewritten by a kernel on `stream` at the start of every
+ * call.  All calls on one GPU share that array, so calls that overlap in
+ * time on one GPU (on different streams, or from different host threads)
+ * race and must not be issued; calls in one stream's order are fine.
+ * Limits (LADL_EUNSUPPORTED beyond them, nothing launched):
+ * 1 <= num_problems <= LADL_NOALLOC_MAX_PROBLEMS, 1 <= n <=
+ * LADL_NOALLOC_MAX_ROWS, 1 <= p <= 32, and one problem's X must fit the LDS
+ * of a compute unit (every n <= 1024, p <= 32 does on MI355X).  Other
+ * errors as for ladl_solve_f32.
+ */
+#define LADL_NOALLOC_MAX_PROBLEMS 65536
+#define LADL_NOALLOC_MAX_ROWS 1024
+int ladl_solve_uniform_noalloc_f32(int32_t num_problems, int32_t n, int32_t p, int32_t path_len,
+                                   const ladl_options *opt, const float *X, const float *y, const float *lambda,
+                                   const float *b_init, float *b, float *obj, uint32_t *active, int32_t *zero_rows,
+                                   int32_t *status, int32_t *iters, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

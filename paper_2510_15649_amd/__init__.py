@@ -30,7 +30,7 @@ EXPORTED = ["ladl_create", "ladl_destroy", "ladl_default_options", "ladl_plan_cr
             "ladl_graph_create", "ladl_graph_launch", "ladl_graph_destroy", "ladl_autotune",
             "ladl_plan_describe", "ladl_error_string", "ladl_last_error_detail", "ladl_cv_create",
             "ladl_cv_destroy", "ladl_cv_run", "ladl_brute_force_f32", "ladl_selection_frequency",
-            "ladl_plan_profile", "ladl_plan_profile_read"]
+            "ladl_solve_uniform_noalloc_f32", "ladl_plan_profile", "ladl_plan_profile_read"]
 
 
 class Options(C.Structure):
@@ -99,6 +99,7 @@ def lib() -> C.CDLL:
     L.ladl_cv_create.argtypes = [vp, C.POINTER(CVLayout), C.POINTER(Options), C.POINTER(vp)]
     L.ladl_cv_destroy.argtypes = [vp]
     L.ladl_cv_run.argtypes = [vp] + [vp] * 7 + [vp]
+    L.ladl_solve_uniform_noalloc_f32.argtypes = [i32, i32, i32, i32, C.POINTER(Options)] + [vp] * 11
     L.ladl_plan_profile.argtypes = [vp, i32]
     L.ladl_plan_profile_read.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(i32), i32, C.POINTER(i32)]
     L.ladl_error_string.argtypes = [C.c_int]
@@ -109,7 +110,7 @@ def lib() -> C.CDLL:
                  "ladl_solve_plain_f32", "ladl_backward_f32", "ladl_graph_create", "ladl_graph_launch",
                  "ladl_graph_destroy", "ladl_autotune", "ladl_plan_describe", "ladl_cv_create", "ladl_cv_destroy",
                  "ladl_cv_run", "ladl_brute_force_f32", "ladl_selection_frequency",
-                 "ladl_plan_profile", "ladl_plan_profile_read"]:
+                 "ladl_solve_uniform_noalloc_f32", "ladl_plan_profile", "ladl_plan_profile_read"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -491,6 +492,41 @@ class CrossValidation:
         if getattr(self, "_cv", None) and _lib is not None:
             _lib.ladl_cv_destroy(self._cv)
             self._cv = None
+
+
+def solve_uniform_noalloc(X, y, lam, num_problems: int, n: int, p: int, path_len: int = 1, b_init=None,
+                          out=None, stream=None, iters=True, options: Optional[Options] = None, **opt_kw):
+    """The allocation-free entry point: num_problems problems of n x p packed
+    back to back, each solved along its path of path_len lambdas.  `out`
+    (or freshly allocated tensors) receives the outputs, laid out as for
+    Plan.solve.  The library allocates nothing during the call."""
+    import torch
+    P, Lp = int(num_problems), int(path_len)
+    n_out = P * Lp
+    opts = options if options is not None else default_options(**opt_kw)
+    _check(X, "X", "f32", P * n * p)
+    _check(y, "y", "f32", P * n)
+    _check(lam, "lam", "f32", n_out)
+    _check(b_init, "b_init", "f32", P * p, optional=True)
+    if out is None:
+        dev = X.device
+        out = dict(b=torch.empty(n_out * p, dtype=torch.float32, device=dev),
+                   obj=torch.empty(n_out, dtype=torch.float32, device=dev),
+                   active=torch.empty(n_out, dtype=torch.int32, device=dev),
+                   zero_rows=torch.empty(n_out * ZPAD, dtype=torch.int32, device=dev),
+                   status=torch.empty(n_out, dtype=torch.int32, device=dev),
+                   iters=torch.empty(n_out * 4, dtype=torch.int32, device=dev) if iters else None)
+    _check(out.get("b"), "b", "f32", n_out * p)
+    _check(out.get("obj"), "obj", "f32", n_out)
+    _check(out.get("active"), "active", "i32", n_out)
+    _check(out.get("zero_rows"), "zero_rows", "i32", ZPAD * n_out)
+    _check(out.get("status"), "status", "i32", n_out)
+    _check(out.get("iters"), "iters", "i32", 4 * n_out, optional=True)
+    check(lib().ladl_solve_uniform_noalloc_f32(P, int(n), int(p), Lp, C.byref(opts), _ptr(X), _ptr(y), _ptr(lam),
+                                              _ptr(b_init), _ptr(out["b"]), _ptr(out["obj"]), _ptr(out["active"]),
+                                              _ptr(out["zero_rows"]), _ptr(out["status"]), _ptr(out.get("iters")),
+                                              _stream(stream)))
+    return out
 
 
 def to_device(w, device="cuda"):

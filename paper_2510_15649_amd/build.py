@@ -8,7 +8,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libladlasso.so")
 
-SOURCES = ["ladl_solve_wave.hip", "ladl_solve_plain.hip", "ladl_cv.hip", "ladl_brute.hip", "ladl_api.cpp"]
+SOURCES = ["ladl_solve_wave.hip", "ladl_solve_plain.hip", "ladl_cv.hip", "ladl_brute.hip", "ladl_noalloc.hip",
+           "ladl_api.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

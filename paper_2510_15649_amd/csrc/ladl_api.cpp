@@ -1122,3 +1122,13 @@ int ladl_selection_frequency(ladl_plan_t pl, const uint32_t *active, const int32
     if (e != hipSuccess) return hipfail(e, "selection frequency launch");
     return LADL_OK;
 }
+
+// --------------------------------------------------------------------------
+// helpers for the other host source files (ladl_host.hpp)
+// --------------------------------------------------------------------------
+namespace ladl {
+int host_fail(int code, const char *msg) { return fail(code, "%s", msg); }
+int host_hipfail(hipError_t e, const char *what) { return hipfail(e, what); }
+int host_check_options(const ladl_options *o) { return check_options(o); }
+DevOpt host_dev_opt(const ladl_options &o) { return dev_opt(o); }
+} // namespace ladl
