@@ -42,7 +42,7 @@ OPS_PER_ROW_UPDATE = 12
 METRIC = "LAD-LASSO solves/sec at 1e-5 rel objective vs plain kernel; achieved HBM GB/s"
 
 # device sources whose hash the committed byte-counter summaries record
-KERNEL_SOURCES = ["ladl_solve_wave.hip", "ladl_wave.hpp", "ladl_common.hpp", "ladl_kernels.hpp"]
+KERNEL_SOURCES = ["ladl_solve_wave.hip", "ladl_wave.hpp", "ladl_team.hpp", "ladl_common.hpp", "ladl_kernels.hpp"]
 
 
 def make_workload(cfg: str):
@@ -188,14 +188,16 @@ def measure(L, torch, w, steps, warmup, parity_solves, autotune=False, **opts):
                 describe=plan.describe())
 
 
-def alu_roofline(m, profile_summary=None, traffic_key=None):
+def alu_roofline(m, profile_summary=None):
     """ALU roofline of the bucket kernel that takes the longest: algorithmic
     lane-ops (OPS_PER_ROW_UPDATE per row of each coordinate update it ran)
-    over its average launch time from HIP events on its own stream."""
+    over its average launch time from HIP events on its own stream.  The
+    HBM traffic of that kernel comes from the committed byte-counter
+    summary (key traffic_bytes_per_launch_R<rows per lane>)."""
     dom = max(m["buckets"], key=lambda b: b["ms_per_launch"])
     ops = OPS_PER_ROW_UPDATE * dom["row_updates"]
     achieved = ops / (dom["ms_per_launch"] / 1e3)
-    traffic = recorded_traffic(profile_summary, traffic_key) if profile_summary else None
+    traffic = recorded_traffic(profile_summary, f"traffic_bytes_per_launch_R{dom['R']}") if profile_summary else None
     return {"bound": "alu", "kernel": f"k_wave bucket R={dom['R']} (n<={dom['n_max']}, p<={dom['p_max']})",
             "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "Tlane-op/s",
             "frac": achieved / PEAK_VALU_LANE_OPS, "traffic": traffic, "ms_per_launch": dom["ms_per_launch"],
@@ -409,6 +411,8 @@ def main():
                     help="waves per solve for n > 1024 (0: the library's choice; 1, 2 or 4)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the HIP-graph replay of the path and the backward (profiling the forward alone)")
     ap.add_argument("--parity-sample", type=int, default=48,
                     help="solves of the headline workload checked against the oracle (plus 16 of the largest "
                          "problems on the ragged batch)")
@@ -445,13 +449,13 @@ def main():
                 flags=flags, team=args.team)
     ms = m["ms"]
     default_run = args.max_rounds == 1 and not args.golden and not args.autotune and args.team == 0
-    summary = {"c4": "k_wave_c4_full_hbm_bytes.md", "c2": "k_wave_c2_hbm_bytes.md",
+    summary = {"c4": "k_wave_c4_full_hbm_bytes.md", "c2": "k_wave_c2_kernel_stats.md",
                "c1": "k_wave_c1_hbm_bytes.md"}.get(args.config) if default_run else None
-    roof = alu_roofline(m, summary, "traffic_bytes_per_launch")
+    roof = alu_roofline(m, summary)
     alg_bytes = w.algorithmic_bytes()
     hbm_gbs = alg_bytes / (ms / 1e3) / 1e9
     graph_ms = graph_same = backward = None
-    if w.path_len > 1 and w.grad_b is not None:
+    if w.path_len > 1 and w.grad_b is not None and not args.no_graph:
         graph_ms, graph_same, backward = path_graph_and_backward(L, torch, w, m)
         if args.config == "c4" and default_run:
             backward["traffic"] = recorded_traffic("k_bw_c4_full_hbm_bytes.md", "backward_traffic_bytes_per_launch")
@@ -480,13 +484,13 @@ def main():
                 plain = plain_comparison(L, torch, s, ws)
                 entry["plain_kernel"] = plain
                 entry["vs_plain"] = s["solves_per_s"] / plain["value"]
-                entry["roofline"] = alu_roofline(s, "k_wave_c1_hbm_bytes.md", "traffic_bytes_per_launch")
+                entry["roofline"] = alu_roofline(s, "k_wave_c1_hbm_bytes.md")
             if cfg == "c2" and mr == 1:
                 gbs = ws.algorithmic_bytes() / (s["ms"] / 1e3) / 1e9
                 entry["hbm"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                 "frac": gbs / PEAK_HBM_GBS, "algorithmic_bytes": ws.algorithmic_bytes(),
-                                "traffic": recorded_traffic("k_wave_c2_hbm_bytes.md", "traffic_bytes_per_launch")}
-                entry["roofline"] = alu_roofline(s)
+                                "traffic": recorded_traffic("k_wave_c2_kernel_stats.md", "traffic_bytes_per_step")}
+                entry["roofline"] = alu_roofline(s, "k_wave_c2_kernel_stats.md")
             if cfg == "c3":
                 entry["backward"] = backward_c3(L, torch, ws, s)
             secondary.append(entry)
