@@ -335,37 +335,41 @@ __device__ bool pt_vertex_eval(PT &t, int s, float &f)
     for (int q = 0; q < s; ++q)
         for (int c = 0; c < s; ++c) t.A[q * ALD + c] = t.x(t.zs[q], t.ss[c]);
     if (!pt_lu(t, s)) return false;
-    float v[PMAX], e[PMAX];
-    for (int q = 0; q < s; ++q) v[q] = t.y[t.zs[q]];
-    pt_solve(t, s, v);
-    // mixed-precision refinement: residual in fp64, until the correction is
-    // at rounding level
+    float e[PMAX];
+    double v[PMAX];
+    for (int q = 0; q < s; ++q) e[q] = t.y[t.zs[q]];
+    pt_solve(t, s, e);
+    for (int q = 0; q < s; ++q) v[q] = (double)e[q];
+    // b_S in fp64 by mixed-precision refinement (fp32 LU, fp64 residuals and
+    // accumulation) until the correction is at fp64 rounding level: the
+    // certificate reads the signs of the other rows' residuals at this vertex
     for (int it = 0; it < REFINE_MAX; ++it) {
         float cm = 0.f, xm = 0.f;
         for (int q = 0; q < s; ++q) {
             double acc = (double)t.y[t.zs[q]];
-            for (int c = 0; c < s; ++c) acc -= (double)t.x(t.zs[q], t.ss[c]) * (double)v[c];
+            for (int c = 0; c < s; ++c) acc -= (double)t.x(t.zs[q], t.ss[c]) * v[c];
             e[q] = (float)acc;
         }
         pt_solve(t, s, e);
         for (int q = 0; q < s; ++q) {
-            v[q] += e[q];
+            v[q] += (double)e[q];
             cm = fmaxf(cm, fabsf(e[q]));
-            xm = fmaxf(xm, fabsf(v[q]));
+            xm = fmaxf(xm, fabsf((float)v[q]));
         }
-        if (cm <= 1e-7f * xm) break;
+        if (cm <= 1e-14f * xm) break;
     }
     for (int j = 0; j < t.p; ++j) t.bt[j] = 0.f;
     for (int c = 0; c < s; ++c) {
-        float bc = v[c];
+        float bc = (float)v[c];
         if (!__builtin_isfinite(bc)) return false;
         t.bt[t.ss[c]] = bc;
     }
-    // residuals in fp64 (stored as fp32): the certificate reads their signs
+    // residuals of the fp64 vertex (stored as fp32): the certificate reads
+    // their signs
     double s64 = 0.0;
     for (int i = 0; i < t.n; ++i) {
         double r = (double)t.y[i];
-        for (int c = 0; c < s; ++c) r = fma(-(double)t.x(i, t.ss[c]), (double)t.bt[t.ss[c]], r);
+        for (int c = 0; c < s; ++c) r = fma(-(double)t.x(i, t.ss[c]), v[c], r);
         t.rv[i] = t.zf[i] ? 0.f : (float)r;
         s64 += t.zf[i] ? 0.0 : fabs(r);
     }

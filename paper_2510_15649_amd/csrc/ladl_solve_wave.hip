@@ -927,8 +927,9 @@ LADL_INL float lu_solve_t(const float *A, const int *piv, int s, float v)
 }
 
 // Vertex (zs, ss, s): A = X_{Z,S} factored in LDS (A0 keeps it unfactored),
-// b_S = A^{-1} y_Z refined with fp64 residuals, b into vt, residuals into rv
-// (exact zeros on Z), objective into f (and in fp64 into w.fv64).
+// b_S = A^{-1} y_Z refined to fp64 accuracy, b (rounded to fp32) into vt,
+// the residuals of the fp64 vertex into rv (exact zeros on Z), objective
+// into f (and in fp64 into w.fv64).
 template <int R, bool XG, int TW>
 LADL_INL bool vertex_eval(Wave<R, XG, TW> &w, float (&rv)[R], uint32_t zbits, int s, float &f)
 {
@@ -955,20 +956,24 @@ LADL_INL bool vertex_eval(Wave<R, XG, TW> &w, float (&rv)[R], uint32_t zbits, in
     __syncthreads();
     if (!lu_factor(w.A, w.piv, s)) return false;
     const float yz = (l < s) ? w.ys[zl] : 0.f;
-    float xs = lu_solve(w.A, w.piv, s, yz);
-    // mixed-precision refinement: residual y_Z - X_{Z,S} b_S in fp64, until
-    // the correction is at rounding level (each step gains a factor of about
-    // cond(X_{Z,S}) * 2^-24, so ill-conditioned vertices take more steps)
+    // b_S in fp64 by mixed-precision refinement: the fp32 LU applied to the
+    // residual y_Z - X_{Z,S} b_S formed in fp64, the correction accumulated
+    // in fp64, until it is at fp64 rounding level (each step gains a factor
+    // of about cond(X_{Z,S}) * 2^-24).  The certificate reads the signs of
+    // the other rows' residuals at this vertex; from an fp32-rounded b a row
+    // 1e-6 (relative) from its hyperplane can show the wrong sign.
+    double xd = (double)lu_solve(w.A, w.piv, s, yz);
     for (int it = 0; it < REFINE_MAX; ++it) {
         double acc = (double)yz;
         for (int c = 0; c < s; ++c) {
-            const float xc = rdlane(xs, c);
-            if (l < s) acc -= (double)w.A0[l * a0ld + c] * (double)xc;
+            const double xc = rdlane_d(xd, c);
+            if (l < s) acc -= (double)w.A0[l * a0ld + c] * xc;
         }
         const float corr = lu_solve(w.A, w.piv, s, (l < s) ? (float)acc : 0.f);
-        xs += corr;
-        if (wmax(fabsf(corr)) <= 1e-7f * wmax(fabsf(xs))) break;
+        xd += (double)corr;
+        if (wmax(fabsf(corr)) <= 1e-14f * wmax(fabsf((float)xd))) break;
     }
+    const float xs = (float)xd;
     if (ballot(l < s && !__builtin_isfinite(xs))) return false;
     if (l < w.p) w.vt[l] = 0.f;
     __syncthreads();
@@ -981,7 +986,7 @@ LADL_INL bool vertex_eval(Wave<R, XG, TW> &w, float (&rv)[R], uint32_t zbits, in
     for (int k = 0; k < R; ++k) racc[k] = (double)w.ys[row_of(w, k)];
     for (int c = 0; c < s; ++c) {
         const int jc = rdlane(jl, c);
-        const double bc = (double)rdlane(xs, c);
+        const double bc = rdlane_d(xd, c);
 #pragma unroll
         for (int k = 0; k < R; ++k) racc[k] = fma(-(double)xget(w, jc, row_of(w, k)), bc, racc[k]);
     }

@@ -112,7 +112,7 @@ def test_c4_full_path_sampled(torch):
     """The whole large ragged workload (65536 problems, 32-value warm-started
     lambda path each, 2,097,152 outputs) in one in-kernel path launch per
     bucket, backward at the last lambda.  Every output is checked for status
-    and consistency; 24 seeded problems of at most 400 rows and 12 features
+    (all certified) and consistency; 24 seeded problems of at most 400 rows and 12 features
     (the oracle's cost grows steeply with n and p) are compared with the
     oracle along their whole path, and their gradient blocks with the
     oracle's vertex-form gradient.  The sample holds 24 problems drawn
@@ -127,9 +127,7 @@ def test_c4_full_path_sampled(torch):
     gy_d, gX_d = plan.backward(d["X"], out, torch.from_numpy(w.grad_b).cuda())
     torch.cuda.synchronize()
     g = to_numpy(out)
-    # two outputs of the 2.1 M are known to end NOTCERTIFIED (flagged, with
-    # objectives within 3e-6 of the certified optimum)
-    check_every_output(w, g, max_flagged=2)
+    check_every_output(w, g)
     Lp = w.path_len
     ns = np.diff(w.row_off)
     rng = np.random.default_rng(23)
