@@ -45,9 +45,9 @@ METRIC = "LAD-LASSO solves/sec at 1e-5 rel objective vs plain kernel; achieved H
 KERNEL_SOURCES = ["ladl_solve_wave.hip", "ladl_wave.hpp", "ladl_team.hpp", "ladl_common.hpp", "ladl_kernels.hpp"]
 
 
-def make_workload(cfg: str):
+def make_workload(cfg: str, **kw):
     from paper_2510_15649_amd import workloads as W
-    return {"c1": lambda: W.config1(), "c1path": lambda: W.config1(as_path=True), "c2": lambda: W.config2(),
+    return {"c1": lambda: W.config1(**kw), "c1path": lambda: W.config1(as_path=True), "c2": lambda: W.config2(),
             "c3": lambda: W.config3(), "c4": lambda: W.config4(),
             "c4s": lambda: W.config4(problems=range(4096))}[cfg]()
 
@@ -392,7 +392,8 @@ def measure_brute(L, torch, steps=3, sample=16):
 
 
 def secondary_entry(w, s, mr, fl):
-    return {"workload": w.name, "max_rounds": mr, "golden": bool(fl), "solves_per_s": s["solves_per_s"],
+    return {"workload": w.name, "max_rounds": mr, "golden": bool(fl & 1), "quadrature": bool(fl & 8),
+            "solves_per_s": s["solves_per_s"],
             "ms_per_step": s["ms"], "parity_ok": s["parity_ok"], "max_rel_f": s["parity"]["max_rel_f"],
             "strict_of_unique": [s["parity"]["strict"], s["parity"]["unique"]],
             "iters_mean": s["iters_mean"], "status": s["status"], "buckets": s["buckets"]}
@@ -407,6 +408,8 @@ def main():
     ap.add_argument("--max-rounds", type=int, default=1)
     ap.add_argument("--golden", action="store_true")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--quadrature", action="store_true",
+                    help="the quadrature variant: 1-D sections minimised by a quadrature search of their values")
     ap.add_argument("--team", type=int, default=0,
                     help="waves per solve for n > 1024 (0: the library's choice; 1, 2 or 4)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -439,7 +442,7 @@ def main():
         return
     log(f"generating workload {args.config}")
     w = make_workload(args.config)
-    flags = L.FLAG_GOLDEN if args.golden else 0
+    flags = (L.FLAG_GOLDEN if args.golden else 0) | (L.FLAG_QUADRATURE if args.quadrature else 0)
     if args.config in ("c4", "c4s"):
         psolves = c4_parity_solves(w, n_uniform=args.parity_sample)
     else:
@@ -448,7 +451,7 @@ def main():
     m = measure(L, torch, w, args.steps, args.warmup, psolves, args.autotune, max_rounds=args.max_rounds,
                 flags=flags, team=args.team)
     ms = m["ms"]
-    default_run = args.max_rounds == 1 and not args.golden and not args.autotune and args.team == 0
+    default_run = args.max_rounds == 1 and flags == 0 and not args.autotune and args.team == 0
     summary = {"c4": "k_wave_c4_full_hbm_bytes.md", "c2": "k_wave_c2_kernel_stats.md",
                "c1": "k_wave_c1_hbm_bytes.md"}.get(args.config) if default_run else None
     roof = alu_roofline(m, summary)
@@ -469,8 +472,8 @@ def main():
     secondary = []
     plain = None
     if not args.no_secondary:
-        for cfg, mr, fl in [("c1", 1, 0), ("c1", 0, 0), ("c1", 1, L.FLAG_GOLDEN), ("c2", 1, 0), ("c2", 0, 0),
-                            ("c3", 1, 0)]:
+        for cfg, mr, fl in [("c1", 1, 0), ("c1", 0, 0), ("c1", 1, L.FLAG_GOLDEN), ("c1", 1, L.FLAG_QUADRATURE),
+                            ("c2", 1, 0), ("c2", 0, 0), ("c3", 1, 0)]:
             if cfg == args.config and mr == args.max_rounds and fl == flags:
                 continue
             log(f"generating workload {cfg}")
@@ -485,6 +488,14 @@ def main():
                 entry["plain_kernel"] = plain
                 entry["vs_plain"] = s["solves_per_s"] / plain["value"]
                 entry["roofline"] = alu_roofline(s, "k_wave_c1_hbm_bytes.md")
+            if cfg == "c1" and fl == L.FLAG_QUADRATURE:
+                # the paper's one-thread-per-problem design with quadrature
+                # sections, on the first 64 of the 512 problems (1024 solves)
+                log("plain kernel with quadrature sections, 1024 solves, median of 3 launches")
+                wq = make_workload("c1", num_problems=64)
+                mq = dict(plan=L.Plan.for_workload(wq, max_rounds=mr, flags=fl), d=L.to_device(wq),
+                          n_out=wq.num_solves * wq.path_len)
+                entry["plain_kernel_1024"] = plain_comparison(L, torch, mq, wq, reps=3, parity=64)
             if cfg == "c2" and mr == 1:
                 gbs = ws.algorithmic_bytes() / (s["ms"] / 1e3) / 1e9
                 entry["hbm"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -506,7 +517,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic (seeded generator, no dataset)",
         "config": {"workload": w.name, "solves_per_step": m["n_out"], "max_rounds": args.max_rounds,
-                   "golden": bool(args.golden), "autotune": bool(args.autotune), "team": args.team,
+                   "golden": bool(args.golden), "quadrature": bool(args.quadrature),
+                   "autotune": bool(args.autotune), "team": args.team,
                    "parallelism": "1 GPU, one wavefront per solve, buckets side by side",
                    "path_len": w.path_len, "graph_ms_per_step": graph_ms, "graph_equals_in_kernel": graph_same},
         "roofline": roof,

@@ -74,8 +74,21 @@ enum {
     LADL_FLAG_GOLDEN = 1,       /* golden-section instead of thirds in the
                                    ternary chop (same limit, fewer probes)   */
     LADL_FLAG_NO_FINISHER = 2,  /* stop after the paper's stages             */
-    LADL_FLAG_NO_SNAP = 4       /* no vertex snap/certificate: b is the last
+    LADL_FLAG_NO_SNAP = 4,      /* no vertex snap/certificate: b is the last
                                    coordinate-descent point, status MAXITER  */
+    LADL_FLAG_QUADRATURE = 8    /* the paper's second variant (Sections 1,
+                                   3.5, 5): every 1-D section is minimised
+                                   by a quadrature search of its values
+                                   (bracket [smallest kink, largest kink],
+                                   halved around the lowest of its three
+                                   quarter points until its width is at most
+                                   2^-22 (1 + |lo| + |hi|); the point is kept
+                                   only if it lowers f) instead of the exact
+                                   weighted median.  The chop, the snap and
+                                   the certificate are unchanged, so results
+                                   are certified as before; the search costs
+                                   about 25 passes over the column per
+                                   update instead of one or two              */
 };
 
 typedef struct {
@@ -177,7 +190,15 @@ int ladl_plan_destroy(ladl_plan_t plan);
 int64_t ladl_plan_b_len(ladl_plan_t plan);
 
 /*
- * Forward solve (the wavefront-per-solve persistent kernels).
+ * Forward solve (the wavefront-per-solve persistent kernels): for every
+ * (solve, path step), minimise f(b) = sum_i |y_i - x_i.b| + lambda ||b||_1
+ * (the LAD-LASSO objective of the Abstract and Sections 2.1, 2.2, 3.1) by
+ * cyclic coordinate descent with exact 1-D section minima (Sections 3.3,
+ * 3.5; or the quadrature search with LADL_FLAG_QUADRATURE), the ternary
+ * chop along the locus of axis-wise minima (Sections 3.5, 3.6), then the
+ * vertex snap, certificate and finisher (Section 3.2's vertex form; the
+ * finisher is this library's addition).  Along a path each step starts
+ * from the previous step's answer (Section 5's regularisation paths).
  *   X, y       device, layout as described by the plan
  *   lambda     device [num_solves * path_len]
  *   b_init     device, packed like one path step of b (p_s floats per solve
@@ -226,7 +247,9 @@ int ladl_backward_f32(ladl_plan_t plan, const float *X, const float *b, const in
 
 /*
  * Lambda path as a HIP graph: path_len launches, one per path step, each
- * warm-started from the previous step's output, captured once and replayed
+ * warm-started from the previous step's output (the regularisation path of
+ * Section 5, computed step by step as ladl_solve_f32 computes it in one
+ * launch; the outputs are bit-identical), captured once and replayed
  * by ladl_graph_launch.  The pointers are baked into the graph: refill the
  * same buffers to run new data of the same layout.
  */
@@ -239,9 +262,12 @@ int ladl_graph_destroy(ladl_graph_t graph);
 /*
  * Time each candidate schedule on this plan's own data (runs the solve
  * several times on `stream`, synchronously) and keep the fastest per
- * bucket in the plan: X resident in LDS, X in the HBM workspace, and (for
+ * bucket in the plan: X resident in LDS, X in the HBM workspace, (for
  * n <= 256) X in the HBM workspace with the 4-waves-per-SIMD kernel
- * variant, for the buckets where more than one exists.  The choice is
+ * variant, and (for n > 1024) teams of 2 or 4 wavefronts per solve, for
+ * the buckets where more than one exists.  The paper leaves the mapping of
+ * problems onto the hardware to the application (coarse parallelism,
+ * Abstract and Section 5); this picks it by measurement.  The choice is
  * cached in the file named by the environment variable LADL_TUNE_CACHE (if
  * set), keyed by device, rows per lane and p_max.  Optional: plans start
  * with a static choice; a plan created with options.schedule = 0 or 1 is

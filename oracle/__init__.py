@@ -20,12 +20,14 @@ _LIB = os.path.join(_HERE, "libladl_oracle.so")
 
 MAX_P = 64
 STAGE_CCD, STAGE_TERNARY, STAGE_FINISHER, STAGE_NONE = 0, 1, 100, -1
+SECTION_MEDIAN, SECTION_QUADRATURE = 0, 1
 
 
 class Opts(C.Structure):
     _fields_ = [("tol_f", C.c_double), ("tol_s", C.c_double), ("lambda_min", C.c_double),
                 ("max_sweeps", C.c_int), ("max_ternary", C.c_int), ("max_rounds", C.c_int),
-                ("max_pivots", C.c_int), ("use_finisher", C.c_int), ("chop_range", C.c_double)]
+                ("max_pivots", C.c_int), ("use_finisher", C.c_int), ("chop_range", C.c_double),
+                ("section", C.c_int), ("tol_q", C.c_double)]
 
 
 class Prob(C.Structure):
@@ -73,6 +75,9 @@ def lib():
         L.orc_weighted_median.restype = C.c_int
         L.orc_coord_update.argtypes = [C.POINTER(Prob), C.c_double, dp, dp, C.c_int]
         L.orc_coord_update.restype = C.c_double
+        L.orc_quadrature_update.argtypes = [C.POINTER(Prob), C.c_double, C.c_double, dp, dp, C.c_int,
+                                            C.POINTER(C.c_long)]
+        L.orc_quadrature_update.restype = C.c_double
         L.orc_ccd.argtypes = [C.POINTER(Prob), C.POINTER(Opts), C.c_double, dp, dp, C.c_int, dp,
                               C.POINTER(C.c_long)]
         L.orc_ccd.restype = C.c_int
@@ -138,6 +143,17 @@ def coord_update(X, y, lam, b, j):
     r = P.y - P.X @ b
     lib().orc_coord_update(C.byref(P.c), float(lam), _d(b), _d(r), int(j))
     return b
+
+
+def quadrature_update(X, y, lam, b, j, tol_q=1e-13):
+    """One coordinate minimisation by the quadrature search of the section's
+    values; returns (new b, number of section values computed)."""
+    P = Problem(X, y, lam)
+    b = np.array(b, dtype=np.float64)
+    r = P.y - P.X @ b
+    ev = C.c_long(0)
+    lib().orc_quadrature_update(C.byref(P.c), float(lam), float(tol_q), _d(b), _d(r), int(j), C.byref(ev))
+    return b, ev.value
 
 
 def ccd(X, y, lam, b0=None, frozen=-1, **opts):

@@ -37,6 +37,8 @@ void orc_default_opts(orc_opts *o)
     o->max_pivots = 0; /* 0: 4*(n+p) */
     o->use_finisher = 1;
     o->chop_range = 1.0 / 32.0;
+    o->section = ORC_SECTION_MEDIAN;
+    o->tol_q = 1e-13;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -177,6 +179,94 @@ double orc_coord_update(const orc_prob *P, double lambda, double *b, double *r, 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Quadrature search of a 1-D section (Section 3.5 names binary, ternary and */
+/* quadrature searches for the sub-space minimisation; Sections 1 and 5      */
+/* name the quadrature variant of the coordinate descent).  Only values of   */
+/* the section g(t) = sum_i |r_i - x_ij (t - b_j)| + lambda |t| are used: no */
+/* ordering or median of the kinks.                                          */
+/*   1. Bracket [lo, hi] = [smallest, largest] of the kinks t_i (x_ij != 0)  */
+/*      and 0 (lambda > 0): g is non-increasing left of every kink and       */
+/*      non-decreasing right of every kink, so a minimiser lies in it.       */
+/*   2. Evaluate g at the three quarter points q1 < q2 < q3.  For convex g,  */
+/*      the lowest of them, q_k, has a minimiser within [q_{k-1}, q_{k+1}]   */
+/*      (q_0 = lo, q_4 = hi): that half of the bracket is kept, and q_k is   */
+/*      its centre, so each further halving costs two new values.            */
+/*   3. Stop when hi - lo <= tol_q (1 + |lo| + |hi|), or when the quarter    */
+/*      points no longer differ from the ends.  Ties go to the centre, then  */
+/*      to the lower quarter point.                                          */
+/*   4. The kept centre replaces b_j only if its value is below g(b_j), so   */
+/*      f never rises.                                                        */
+/* ------------------------------------------------------------------------ */
+
+static double section_value(const orc_prob *P, double lam, const double *b, const double *r, int j,
+                            double t)
+{
+    const double d = t - b[j];
+    double s = 0.0, c = 0.0;
+    for (int i = 0; i < P->n; ++i) neumaier(&s, &c, fabs(r[i] - XIJ(P, i, j) * d));
+    neumaier(&s, &c, lam * fabs(t));
+    return s + c;
+}
+
+static double coord_update_q(const orc_prob *P, double lam, double tol_q, double *b, double *r, int j,
+                             long *evals)
+{
+    const int n = P->n;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = 0; i < n; ++i) {
+        double x = XIJ(P, i, j);
+        if (x != 0.0) {
+            double t = b[j] + r[i] / x;
+            lo = fmin(lo, t);
+            hi = fmax(hi, t);
+        }
+    }
+    if (lam > 0.0) {
+        lo = fmin(lo, 0.0);
+        hi = fmax(hi, 0.0);
+    }
+    if (!(lo <= hi)) return 0.0; /* section is flat: keep b_j */
+    long ev = 0;
+    double mid = 0.5 * (lo + hi);
+    double gm = section_value(P, lam, b, r, j, mid);
+    ++ev;
+    for (int it = 0; it < 4096; ++it) {
+        if (hi - lo <= tol_q * (1.0 + fabs(lo) + fabs(hi))) break;
+        double q1 = 0.5 * (lo + mid), q3 = 0.5 * (mid + hi);
+        if (!(q1 > lo && q1 < mid && q3 > mid && q3 < hi)) break;
+        double g1 = section_value(P, lam, b, r, j, q1);
+        double g3 = section_value(P, lam, b, r, j, q3);
+        ev += 2;
+        if (g1 < gm && g1 <= g3) { /* [lo, mid] around q1 */
+            hi = mid;
+            mid = q1;
+            gm = g1;
+        } else if (g3 < gm) { /* [mid, hi] around q3 */
+            lo = mid;
+            mid = q3;
+            gm = g3;
+        } else { /* [q1, q3] around mid */
+            lo = q1;
+            hi = q3;
+        }
+    }
+    double g0 = section_value(P, lam, b, r, j, b[j]);
+    ++ev;
+    if (evals) *evals += ev;
+    if (!(gm < g0)) return 0.0;
+    double d = mid - b[j];
+    for (int i = 0; i < n; ++i) r[i] -= XIJ(P, i, j) * d;
+    b[j] = mid;
+    return d;
+}
+
+double orc_quadrature_update(const orc_prob *P, double lambda, double tol_q, double *b, double *r, int j,
+                             long *evals)
+{
+    return coord_update_q(P, lambda, tol_q, b, r, j, evals);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Cyclical coordinate descent (Section 3.3); axis `frozen` is held fixed,   */
 /* which is the restricted sub-search of Section 3.6.  Stops after a sweep   */
 /* that changes nothing or lowers f by at most tol_f * f.                     */
@@ -191,7 +281,10 @@ static int ccd_w(const orc_prob *P, const orc_opts *o, double lam, double *b, do
         int changed = 0;
         for (int j = 0; j < P->p; ++j) {
             if (j == frozen) continue;
-            if (coord_update_w(P, lam, b, r, j, k) != 0.0) changed = 1;
+            const double d = o->section == ORC_SECTION_QUADRATURE
+                                 ? coord_update_q(P, lam, o->tol_q, b, r, j, NULL)
+                                 : coord_update_w(P, lam, b, r, j, k);
+            if (d != 0.0) changed = 1;
             if (updates) ++*updates;
         }
         ++sweeps;

@@ -46,7 +46,15 @@ typedef struct {
     int max_pivots;    /* edge-descent finisher pivot cap                          */
     int use_finisher;  /* 1: run the finisher when the paper's stages fail         */
     double chop_range; /* initial chop half-width, a fraction of max(1, |b_k|)     */
+    int section;       /* 1-D section minimiser: ORC_SECTION_*                     */
+    double tol_q;      /* quadrature bracket stops at hi-lo <= tol_q*(1+|lo|+|hi|) */
 } orc_opts;
+
+/* how CCD minimises each 1-D section */
+enum {
+    ORC_SECTION_MEDIAN = 0,     /* exact lower weighted median of the kinks        */
+    ORC_SECTION_QUADRATURE = 1  /* quadrature search on section values (Sec. 3.5)  */
+};
 
 /* stage codes reported by orc_solve */
 enum {
@@ -89,6 +97,15 @@ int orc_weighted_median(int m, const double *t, const double *w);
  * 1-D section minimised exactly, Section 3.5).  Updates b[j] and r = y - Xb.
  * Returns the change of b[j]. */
 double orc_coord_update(const orc_prob *P, double lambda, double *b, double *r, int j);
+
+/* One coordinate minimisation of f along axis j by the quadrature search of
+ * the section's values (Sections 1, 3.5 and 5; the bracket, the halving rule
+ * and the stopping rule are written out in the source).  Updates b[j] and
+ * r = y - Xb unless the search finds no value below f at the current b_j.
+ * Returns the change of b[j]; *evals (nullable) is increased by the number
+ * of section values computed. */
+double orc_quadrature_update(const orc_prob *P, double lambda, double tol_q, double *b, double *r, int j,
+                             long *evals);
 
 /* Cyclic coordinate descent with one optional frozen axis (-1 = none).
  * Returns the number of sweeps; *f receives the objective. */

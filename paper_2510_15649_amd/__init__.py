@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libladlasso.so")
 CERTIFIED, NONUNIQUE, MAXITER, NONFINITE, BADLAMBDA, NOTCERTIFIED = range(6)
 STATUS_NAMES = ["CERTIFIED", "NONUNIQUE", "MAXITER", "NONFINITE", "BADLAMBDA", "NOTCERTIFIED"]
 # option flags
-FLAG_GOLDEN, FLAG_NO_FINISHER, FLAG_NO_SNAP = 1, 2, 4
+FLAG_GOLDEN, FLAG_NO_FINISHER, FLAG_NO_SNAP, FLAG_QUADRATURE = 1, 2, 4, 8
 # return codes
 OK, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, -1, -2, -3, -4
 ZPAD = 32

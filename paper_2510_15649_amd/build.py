@@ -2,6 +2,7 @@
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -22,17 +23,22 @@ FLAGS = [
 
 def build(verbose: bool = False, extra=(), out: str = LIB) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
     bdir = os.path.join(CSRC, "_build")
     os.makedirs(bdir, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(bdir, src + ".o")
-        cmd = [hipcc, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-I",
-               os.path.join(ROOT, "include"), "-I", CSRC, "-o", obj]
+    objs = [os.path.join(bdir, src + ".o") for src in SOURCES]
+    cmds = [[hipcc, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-I", os.path.join(ROOT, "include"),
+             "-I", CSRC, "-o", obj] for src, obj in zip(SOURCES, objs)]
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+    # the translation units compile side by side (the wavefront kernel's
+    # variants dominate the build time)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        codes = list(ex.map(subprocess.call, cmds))
+    for cmd, rc in zip(cmds, codes):
+        if rc != 0:
+            raise subprocess.CalledProcessError(rc, cmd)
     tmp = out + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-fPIC", "-shared", "-o", tmp, *objs]
     if verbose:

@@ -36,7 +36,7 @@ int hipfail(hipError_t e, const char *what)
     return fail(LADL_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-constexpr int KNOWN_FLAGS = LADL_FLAG_GOLDEN | LADL_FLAG_NO_FINISHER | LADL_FLAG_NO_SNAP;
+constexpr int KNOWN_FLAGS = LADL_FLAG_GOLDEN | LADL_FLAG_NO_FINISHER | LADL_FLAG_NO_SNAP | LADL_FLAG_QUADRATURE;
 constexpr int NMAX_ROWS = 2048;     // rows per problem (32 slots x 64 lanes)
 constexpr size_t LDS_RESIDENT_MAX = 40 * 1024; // larger buckets keep X in the global workspace
 constexpr int DENSE_MIN_ROUNDS = 2;             // solves per wave above which the dense variant is used
@@ -502,7 +502,8 @@ static void set_schedule(ladl_plan_t pl, Bucket &b, bool xg, bool dense, int tw)
     b.dense = dense && b.tw == 1 && wave_has_dense(b.R);
     b.nlds = b.xg ? 0 : b.pmax;
     const int Rw = b.R / b.tw; // row slots per lane of each wave
-    b.per_cu = std::max(1, wave_max_blocks_per_cu(b.R, b.pmax, b.xg, b.dense, b.tw, b.nlds));
+    const bool quad = (pl->opt.flags & LADL_FLAG_QUADRATURE) != 0;
+    b.per_cu = std::max(1, wave_max_blocks_per_cu(b.R, b.pmax, b.xg, b.dense, b.tw, quad, b.nlds));
     // With the workspace, keep in LDS as many leading columns of X as the
     // LDS left over at this occupancy holds.  Where buckets run side by side
     // that LDS is what lets the other buckets' waves share a CU, so there
@@ -512,7 +513,7 @@ static void set_schedule(ladl_plan_t pl, Bucket &b, bool xg, bool dense, int tw)
     // them).
     const bool take = !pl->multi_bucket || b.R >= 32;
     while (take && b.xg && b.nlds < b.pmax && wave_lds_bytes(Rw, b.pmax, true, b.nlds + 1, b.tw) <= pl->h->lds_max &&
-           wave_max_blocks_per_cu(b.R, b.pmax, true, b.dense, b.tw, b.nlds + 1) >= b.per_cu)
+           wave_max_blocks_per_cu(b.R, b.pmax, true, b.dense, b.tw, quad, b.nlds + 1) >= b.per_cu)
         ++b.nlds;
     b.grid = (int)std::min<int64_t>(b.count, (int64_t)b.per_cu * pl->h->num_cu);
 }
@@ -530,7 +531,7 @@ static hipError_t launch_bucket(ladl_plan_t pl, size_t bi, const SolveArgs &base
         a.gws = pl->d_wws + bk.ws_off;
         a.gws_stride = (int64_t)wave_ws_floats_host(bk.R / bk.tw, bk.pmax, bk.nlds, bk.tw);
     }
-    return launch_wave(bk.R, bk.xg, bk.dense, bk.tw, a, bk.grid, s);
+    return launch_wave(bk.R, bk.xg, bk.dense, bk.tw, (pl->opt.flags & LADL_FLAG_QUADRATURE) != 0, a, bk.grid, s);
 }
 
 static int enqueue_wave(ladl_plan_t pl, const float *X, const float *y, const float *lam, const float *b_init,

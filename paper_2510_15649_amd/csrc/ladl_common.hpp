@@ -11,7 +11,7 @@ namespace ladl {
 
 constexpr float FINF_C = __builtin_inff();
 
-constexpr int FLAG_GOLDEN = 1, FLAG_NO_FINISHER = 2, FLAG_NO_SNAP = 4;
+constexpr int FLAG_GOLDEN = 1, FLAG_NO_FINISHER = 2, FLAG_NO_SNAP = 4, FLAG_QUADRATURE = 8;
 enum { ST_CERTIFIED = 0, ST_NONUNIQUE = 1, ST_MAXITER = 2, ST_NONFINITE = 3, ST_BADLAMBDA = 4, ST_NOTCERT = 5 };
 
 // optimality certificate slack: the dual sums are accumulated in fp64 and
@@ -40,6 +40,15 @@ constexpr int STALLS_STICKY = 4;
 constexpr int REFINE_MAX = 8; // refinement steps of the vertex and dual solves
 
 #define LADL_INL __device__ __attribute__((always_inline)) inline
+
+// Quadrature search of a 1-D section (the paper's second coordinate-descent
+// variant, Sections 1, 3.5 and 5): the bracket [smallest kink, largest kink]
+// is halved around the lowest of its three quarter points until its width
+// is at most QUAD_TOL (1 + |lo| + |hi|), or QUAD_MAX halvings.  QUAD_TOL is
+// 2^-22: a few units in the last place of fp32, below which the fp32 sums
+// of the section values no longer order the points reliably.
+constexpr float QUAD_TOL = 2.384185791015625e-07f;
+constexpr int QUAD_MAX = 64;
 
 
 // deterministic perturbation direction of row i for degenerate vertices:

@@ -77,15 +77,17 @@ struct BruteArgs {
 // waves per solve (a team of tw waves, each with Rt / tw row slots per
 // lane); xg = X held in a per-team global workspace instead of LDS
 // (required for Rt = 32), except its first nlds columns; dense = the
-// variant compiled for 4 waves per SIMD (Rt <= 4 with xg, tw = 1).  LDS and
-// workspace sizes take the per-wave R = Rt / tw.
+// variant compiled for 4 waves per SIMD (Rt <= 4 with xg, tw = 1); quad:
+// the variant whose 1-D sections are minimised by the quadrature search
+// (every combination exists in both forms).  LDS and workspace sizes take
+// the per-wave R = Rt / tw.
 size_t wave_lds_bytes(int R, int pmax, bool xg, int nlds, int tw);
 size_t wave_ws_floats_host(int R, int pmax, int nlds, int tw);
 bool wave_has_dense(int Rt);
 bool wave_has_team(int Rt, int tw);
-int wave_max_blocks_per_cu(int Rt, int pmax, bool xg, bool dense, int tw, int nlds);
+int wave_max_blocks_per_cu(int Rt, int pmax, bool xg, bool dense, int tw, bool quad, int nlds);
 hipError_t launch_reset(int32_t *counters, int n, hipStream_t s);
-hipError_t launch_wave(int Rt, bool xg, bool dense, int tw, const SolveArgs &a, int grid, hipStream_t s);
+hipError_t launch_wave(int Rt, bool xg, bool dense, int tw, bool quad, const SolveArgs &a, int grid, hipStream_t s);
 hipError_t launch_plain(const SolveArgs &a, int NM, int64_t nthreads, hipStream_t s);
 int64_t plain_scratch_floats(int NM, int64_t nthreads);
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);

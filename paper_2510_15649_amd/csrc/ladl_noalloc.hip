@@ -121,6 +121,7 @@ int ladl_solve_uniform_noalloc_f32(int32_t num_problems, int32_t n, int32_t p, i
     if (opt) o = *opt;
     int rc = host_check_options(&o);
     if (rc != LADL_OK) return rc;
+    const bool quad = (o.flags & LADL_FLAG_QUADRATURE) != 0;
     if (!X || !y || !lambda || !b || !obj || !active || !zero_rows || !status)
         return host_fail(LADL_EINVAL, "a required device pointer is NULL");
     if (((uintptr_t)X | (uintptr_t)y | (uintptr_t)lambda | (uintptr_t)b_init | (uintptr_t)b | (uintptr_t)obj |
@@ -131,7 +132,7 @@ int ladl_solve_uniform_noalloc_f32(int32_t num_problems, int32_t n, int32_t p, i
     const int R = rows_per_lane(n);
     if (wave_lds_bytes(R, p, false, 0, 1) > d.lds_max)
         return host_fail(LADL_EUNSUPPORTED, "X of one problem does not fit the LDS of a CU");
-    const int per_cu = std::max(1, wave_max_blocks_per_cu(R, p, false, false, 1, 0));
+    const int per_cu = std::max(1, wave_max_blocks_per_cu(R, p, false, false, 1, quad, 0));
     const int grid = (int)std::min<int64_t>(num_problems, (int64_t)per_cu * d.num_cu);
     hipStream_t s = (hipStream_t)stream;
     const int setup_blocks = std::min(1024, (num_problems + 1 + 255) / 256);
@@ -166,7 +167,7 @@ int ladl_solve_uniform_noalloc_f32(int32_t num_problems, int32_t n, int32_t p, i
     a.opt = host_dev_opt(o);
     a.pmax = p;
     a.nlds = p;
-    e = launch_wave(R, false, false, 1, a, grid, s);
+    e = launch_wave(R, false, false, 1, quad, a, grid, s);
     if (e != hipSuccess) return host_hipfail(e, "solve kernel launch");
     return LADL_OK;
 }

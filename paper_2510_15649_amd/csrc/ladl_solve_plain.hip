@@ -181,13 +181,84 @@ __device__ bool pt_coord_update(PT &t, int j)
     return true;
 }
 
+// sum_i |r_i - x_ij d| for three offsets d of b_j at once (one pass over
+// the column)
+__device__ void pt_section3(PT &t, int j, float d0, float d1, float d2, float &g0, float &g1, float &g2)
+{
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    for (int i = 0; i < t.n; ++i) {
+        const float r = t.r[i], x = t.x(i, j);
+        s0 += fabsf(fmaf(-x, d0, r));
+        s1 += fabsf(fmaf(-x, d1, r));
+        s2 += fabsf(fmaf(-x, d2, r));
+    }
+    g0 = s0;
+    g1 = s1;
+    g2 = s2;
+}
+
+// minimisation along axis j by the quadrature search of the section's
+// values (no kink is stored, sorted or selected): bracket [lo, hi] from the
+// smallest and largest kink; halve it around the lowest of its quarter
+// points; keep the result only if it lowers f
+__device__ bool pt_coord_update_quad(PT &t, int j)
+{
+    const float bj = t.b[j], lam = t.lam;
+    float lo = FINF_C, hi = -FINF_C;
+    for (int i = 0; i < t.n; ++i) {
+        const float x = t.x(i, j);
+        if (x != 0.f) {
+            const float k = bj + t.r[i] / x;
+            lo = fminf(lo, k);
+            hi = fmaxf(hi, k);
+        }
+    }
+    if (lam > 0.f) {
+        lo = fminf(lo, 0.f);
+        hi = fmaxf(hi, 0.f);
+    }
+    if (!(lo <= hi)) return false;
+    float mid = 0.5f * (lo + hi), g0, gm, gu;
+    pt_section3(t, j, 0.f, mid - bj, 0.f, g0, gm, gu);
+    g0 += lam * fabsf(bj);
+    gm += lam * fabsf(mid);
+    for (int it = 0; it < QUAD_MAX; ++it) {
+        if (hi - lo <= QUAD_TOL * (1.f + fabsf(lo) + fabsf(hi))) break;
+        const float q1 = 0.5f * (lo + mid), q3 = 0.5f * (mid + hi);
+        if (!(q1 > lo && q1 < mid && q3 > mid && q3 < hi)) break;
+        float g1, g3;
+        pt_section3(t, j, q1 - bj, q3 - bj, 0.f, g1, g3, gu);
+        g1 += lam * fabsf(q1);
+        g3 += lam * fabsf(q3);
+        if (g1 < gm && g1 <= g3) {
+            hi = mid;
+            mid = q1;
+            gm = g1;
+        } else if (g3 < gm) {
+            lo = mid;
+            mid = q3;
+            gm = g3;
+        } else {
+            lo = q1;
+            hi = q3;
+        }
+    }
+    if (!(gm < g0)) return false;
+    const float d = mid - bj;
+    if (d == 0.f || !__builtin_isfinite(d)) return false;
+    for (int i = 0; i < t.n; ++i) t.r[i] = fmaf(-t.x(i, j), d, t.r[i]);
+    t.b[j] = mid;
+    return true;
+}
+
 __device__ float pt_ccd(PT &t, int frozen, float f)
 {
+    const bool quad = (t.opt.flags & FLAG_QUADRATURE) != 0;
     for (int sw = 0; sw < t.opt.max_sweeps; ++sw) {
         bool changed = false;
         for (int j = 0; j < t.p; ++j) {
             if (j == frozen) continue;
-            changed |= pt_coord_update(t, j);
+            changed |= quad ? pt_coord_update_quad(t, j) : pt_coord_update(t, j);
             t.c_updates++;
         }
         t.c_sweeps++;

@@ -426,16 +426,17 @@ LADL_INL Sel wselect(Wave<R, XG, TW> &w, const float (&a)[R], const float (&x)[R
     for (int it = 0; it < 3; ++it) {
         float m = FINF;
 #pragma unroll
-        for (int k = 0; k < R; ++k) m = (a[k] > lo && a[k] < m) ? a[k] : m;
-        m = (av > lo && av < m) ? av : m;
+        for (int k = 0; k < R; ++k) m = fminf(m, (a[k] > lo) ? a[k] : FINF);
+        m = fminf(m, (av > lo) ? av : FINF);
         m = tmin_nn(w.tm, m);
         if (m == FINF) {
             if (lo < 0.f) return Sel{FINF, 0, 0, -1, false}; // no candidate at all
             return owner_of(w, a, av, lo);                  // weight exhausted by rounding
         }
+        // keys equal to the finite m are real kinks: their weight is |x|
         float wm = 0.f;
 #pragma unroll
-        for (int k = 0; k < R; ++k) wm += (a[k] == m) ? wt(k) : 0.f;
+        for (int k = 0; k < R; ++k) wm += (a[k] == m) ? fabsf(x[k]) : 0.f;
         wm += (av == m) ? wv : 0.f;
         wm = tsum(w.tm, wm);
         if (reached(cum + wm)) return owner_of(w, a, av, m);
@@ -586,7 +587,6 @@ LADL_INL bool coord_update(Wave<R, XG, TW> &w, float (&r)[R], float &bv, int j, 
     const int l = lane_id();
     // pass 1: weight of the kinks below and at the current b_j (signs only)
     float bel = 0.f, at = 0.f;
-    uint32_t negb = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const float rr = r[k], ax = fabsf(x[k]);
@@ -595,7 +595,6 @@ LADL_INL bool coord_update(Wave<R, XG, TW> &w, float (&r)[R], float &bv, int j, 
         const float wz = z ? ax : 0.f;
         at += wz;
         bel += neg ? ax - wz : 0.f;
-        negb |= (uint32_t)neg << k;
     }
     const float bj = rdlane(bv, j);
     tsum2(w.tm, bel, at);
@@ -615,17 +614,21 @@ LADL_INL bool coord_update(Wave<R, XG, TW> &w, float (&r)[R], float &bv, int j, 
     const float T = down ? (belT - half) : (half - belT - atT);
     auto reached = [&](float c) { return down ? (c > T) : (c >= T); };
     // pass 2: the kinks on the moving side, as distances from b_j, and each
-    // lane's nearest one with the weight of all its kinks at that distance
-    const uint32_t dmask = down ? 0xFFFFFFFFu : 0u;
+    // lane's nearest one with the weight of all its kinks at that distance.
+    // The kink of row i sits at b_j + r_i/x_ij; with the sign flipped when
+    // moving down, it lies on the moving side iff the flipped offset is > 0
+    // (r_i = 0 gives 0: that kink is at b_j, already weighed; x_ij = 0 gives
+    // an infinite offset or NaN: no kink).  The distance |r_i| rcp(|x_ij|)
+    // is the same float either way.
+    const int flip = down ? (int)0x80000000 : 0;
     float a[R];
     float smin = FINF, sw = 0.f;
     int sk = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const float ax = fabsf(x[k]);
-        const bool side = ((negb ^ dmask) >> k) & 1u ? false : true;
-        const bool valid = side && r[k] != 0.f && ax != 0.f;
-        const float ak = valid ? fabsf(r[k]) * __builtin_amdgcn_rcpf(ax) : FINF;
+        const float off = bitsf(fbits(r[k] * __builtin_amdgcn_rcpf(x[k])) ^ flip);
+        const float ak = (off > 0.f) ? off : FINF;
         a[k] = ak;
         const bool lt = ak < smin, eq = ak == smin;
         sw = lt ? ax : (eq ? sw + ax : sw);
@@ -707,8 +710,96 @@ LADL_INL bool coord_update(Wave<R, XG, TW> &w, float (&r)[R], float &bv, int j, 
     return true;
 }
 
-// H5: cyclic sweeps, axis `frozen` held fixed
+// H4, quadrature variant (the paper's second coordinate-descent algorithm,
+// Sections 1, 3.5 and 5): the section g(t) = sum_i |r_i - x_ij (t - b_j)| +
+// lambda |t| is minimised from its values alone, with no ordering or
+// selection of its kinks.  The bracket [smallest kink, largest kink] (and 0
+// when lambda > 0) holds a minimiser; each step evaluates g at the two new
+// quarter points of the bracket and keeps the half centred on the lowest of
+// its three quarter points, so two sums over the rows per halving.  The
+// point reached replaces b_j only if it lowers f.
+// --------------------------------------------------------------------------
 template <int R, bool XG, int TW>
+LADL_INL bool coord_update_quad(Wave<R, XG, TW> &w, float (&r)[R], float &bv, int j, const float (&x)[R])
+{
+    const int ns = w.nslot;
+    const float bj = rdlane(bv, j);
+    const float lam = w.lam;
+    float lo = FINF, hi = -FINF;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if (k >= ns) break;
+        if (x[k] != 0.f) {
+            const float t = fmaf(r[k], __builtin_amdgcn_rcpf(x[k]), bj);
+            lo = fminf(lo, t);
+            hi = fmaxf(hi, t);
+        }
+    }
+    lo = tmin(w.tm, lo);
+    hi = tmax(w.tm, hi);
+    if (lam > 0.f) {
+        lo = fminf(lo, 0.f);
+        hi = fmaxf(hi, 0.f);
+    }
+    if (!(lo <= hi)) return false;
+    float mid = 0.5f * (lo + hi);
+    float g0 = 0.f, gm = 0.f;
+    {
+        const float dm = mid - bj;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (k >= ns) break;
+            g0 += fabsf(r[k]);
+            gm += fabsf(fmaf(-x[k], dm, r[k]));
+        }
+    }
+    tsum2(w.tm, g0, gm);
+    g0 += lam * fabsf(bj);
+    gm += lam * fabsf(mid);
+    for (int it = 0; it < QUAD_MAX; ++it) {
+        if (hi - lo <= QUAD_TOL * (1.f + fabsf(lo) + fabsf(hi))) break;
+        const float q1 = 0.5f * (lo + mid), q3 = 0.5f * (mid + hi);
+        if (!(q1 > lo && q1 < mid && q3 > mid && q3 < hi)) break;
+        const float d1 = q1 - bj, d3 = q3 - bj;
+        float g1 = 0.f, g3 = 0.f;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (k >= ns) break;
+            g1 += fabsf(fmaf(-x[k], d1, r[k]));
+            g3 += fabsf(fmaf(-x[k], d3, r[k]));
+        }
+        tsum2(w.tm, g1, g3);
+        g1 += lam * fabsf(q1);
+        g3 += lam * fabsf(q3);
+        if (g1 < gm && g1 <= g3) {
+            hi = mid;
+            mid = q1;
+            gm = g1;
+        } else if (g3 < gm) {
+            lo = mid;
+            mid = q3;
+            gm = g3;
+        } else {
+            lo = q1;
+            hi = q3;
+        }
+    }
+    if (!(gm < g0)) return false;
+    const float d = mid - bj;
+    if (d == 0.f || !__builtin_isfinite(d)) return false;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if (k >= ns) break;
+        r[k] = fmaf(-x[k], d, r[k]);
+    }
+    bv = (lane_id() == j) ? mid : bv;
+    return true;
+}
+
+// H5: cyclic sweeps, axis `frozen` held fixed; Q selects the quadrature
+// search for the 1-D sections (a kernel variant of its own, so that the
+// exact-median kernels keep their register allocation)
+template <bool Q, int R, bool XG, int TW>
 LADL_INL float ccd(Wave<R, XG, TW> &w, float (&r)[R], float &bv, int frozen, float f)
 {
     const int p = w.p;
@@ -733,7 +824,7 @@ LADL_INL float ccd(Wave<R, XG, TW> &w, float (&r)[R], float &bv, int frozen, flo
             if (!XG) {
                 float xp[R];
                 xcol_lds(w, jn, xp);
-                changed |= coord_update(w, r, bv, u, x);
+                changed |= Q ? coord_update_quad(w, r, bv, u, x) : coord_update(w, r, bv, u, x);
 #pragma unroll
                 for (int k = 0; k < R; ++k) x[k] = xp[k];
             } else {
@@ -745,7 +836,7 @@ LADL_INL float ccd(Wave<R, XG, TW> &w, float (&r)[R], float &bv, int frozen, flo
                     for (int k = 0; k < R; ++k) xc[k] = xn[k];
                 }
                 if (jn >= w.nlds) xcol_ws(w, jn, xn);
-                changed |= coord_update(w, r, bv, u, xc);
+                changed |= Q ? coord_update_quad(w, r, bv, u, xc) : coord_update(w, r, bv, u, xc);
             }
             w.c_updates++;
         }
@@ -1291,7 +1382,7 @@ LADL_INL float objective64(Wave<R, XG, TW> &w, float bval)
 // --------------------------------------------------------------------------
 // one solve (all its path steps)
 // --------------------------------------------------------------------------
-template <int R, bool XG, int TW>
+template <bool Q, int R, bool XG, int TW>
 LADL_INL void solve_item(Wave<R, XG, TW> &w, const SolveArgs &a, int s)
 {
     constexpr int RT = Wave<R, XG, TW>::RT;
@@ -1345,7 +1436,7 @@ LADL_INL void solve_item(Wave<R, XG, TW> &w, const SolveArgs &a, int s)
             int frozen = -1, round = 0, kax = 0;
             float fbest = FINF;
             for (;;) {
-                f = ccd(w, r, bv, frozen, f); // the only CCD call site
+                f = ccd<Q>(w, r, bv, frozen, f); // the only CCD call site
                 float sprobe = 0.f;
                 bool more;
                 if (phase == 0) {
@@ -1508,7 +1599,7 @@ __host__ __device__ constexpr int waves_per_eu(int R, bool dense)
     return dense ? DENSE_WAVES_PER_SIMD : (R >= 32 ? R32_WAVES_PER_SIMD : (R == 8 ? R8_WAVES_PER_SIMD : 1));
 }
 
-template <int R, bool XG, bool DENSE, int TW>
+template <int R, bool XG, bool DENSE, int TW, bool Q>
 __global__ __launch_bounds__(64 * TW) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R, DENSE))))
 void k_wave(SolveArgs a)
 {
@@ -1531,7 +1622,7 @@ void k_wave(SolveArgs a)
             q = uni(w.qw[0]);
         }
         if (q >= a.num_items) break;
-        solve_item(w, a, a.order[q]);
+        solve_item<Q>(w, a, a.order[q]);
     }
 }
 
@@ -1553,27 +1644,27 @@ hipError_t launch_reset(int32_t *counters, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int R, bool XG, bool DENSE, int TW>
+template <int R, bool XG, bool DENSE, int TW, bool Q>
 static hipError_t launch_wave_t(const SolveArgs &a, int grid, hipStream_t s)
 {
     size_t lds = wave_lds_bytes(R, a.pmax, XG, a.nlds, TW);
     static bool attr = false;
     if (!attr) {
         // allow dynamic LDS beyond the default limit; harmless if refused
-        (void)hipFuncSetAttribute((const void *)k_wave<R, XG, DENSE, TW>,
+        (void)hipFuncSetAttribute((const void *)k_wave<R, XG, DENSE, TW, Q>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((k_wave<R, XG, DENSE, TW>), dim3(grid), dim3(64 * TW), lds, s, a);
+    hipLaunchKernelGGL((k_wave<R, XG, DENSE, TW, Q>), dim3(grid), dim3(64 * TW), lds, s, a);
     return hipGetLastError();
 }
 
-template <int R, bool XG, bool DENSE, int TW>
+template <int R, bool XG, bool DENSE, int TW, bool Q>
 static int max_blocks_t(int pmax, int nlds)
 {
     int nb = 0;
     size_t lds = wave_lds_bytes(R, pmax, XG, nlds, TW);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_wave<R, XG, DENSE, TW>, 64 * TW, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_wave<R, XG, DENSE, TW, Q>, 64 * TW, lds) != hipSuccess)
         return 0;
     return nb;
 }
@@ -1587,78 +1678,90 @@ bool wave_has_team(int Rt, int tw) { return tw == 1 || (Rt == 32 && (tw == 2 || 
 // the variants that exist: R in {1,2,4,8,16} with X in LDS or HBM, R = 32
 // with X in HBM, the dense register budget for R <= 4 with X in HBM, and the
 // teams of the n > 1024 bucket (2 x 16, 4 x 8 rows per lane) with X in HBM
-hipError_t launch_wave(int Rt, bool xg, bool dense, int tw, const SolveArgs &a, int grid, hipStream_t s)
+template <bool Q>
+static hipError_t launch_wave_q(int Rt, bool xg, bool dense, int tw, const SolveArgs &a, int grid, hipStream_t s)
 {
     if (tw == 2 || tw == 4) {
         if (!xg || dense || Rt != 32) return hipErrorInvalidValue;
-        return tw == 2 ? launch_wave_t<16, true, false, 2>(a, grid, s) : launch_wave_t<8, true, false, 4>(a, grid, s);
+        return tw == 2 ? launch_wave_t<16, true, false, 2, Q>(a, grid, s) : launch_wave_t<8, true, false, 4, Q>(a, grid, s);
     }
     if (tw != 1) return hipErrorInvalidValue;
     if (dense) {
         if (!xg) return hipErrorInvalidValue;
         switch (Rt) {
-        case 1: return launch_wave_t<1, true, true, 1>(a, grid, s);
-        case 2: return launch_wave_t<2, true, true, 1>(a, grid, s);
-        case 4: return launch_wave_t<4, true, true, 1>(a, grid, s);
+        case 1: return launch_wave_t<1, true, true, 1, Q>(a, grid, s);
+        case 2: return launch_wave_t<2, true, true, 1, Q>(a, grid, s);
+        case 4: return launch_wave_t<4, true, true, 1, Q>(a, grid, s);
         default: return hipErrorInvalidValue;
         }
     }
     if (xg) {
         switch (Rt) {
-        case 1: return launch_wave_t<1, true, false, 1>(a, grid, s);
-        case 2: return launch_wave_t<2, true, false, 1>(a, grid, s);
-        case 4: return launch_wave_t<4, true, false, 1>(a, grid, s);
-        case 8: return launch_wave_t<8, true, false, 1>(a, grid, s);
-        case 16: return launch_wave_t<16, true, false, 1>(a, grid, s);
-        case 32: return launch_wave_t<32, true, false, 1>(a, grid, s);
+        case 1: return launch_wave_t<1, true, false, 1, Q>(a, grid, s);
+        case 2: return launch_wave_t<2, true, false, 1, Q>(a, grid, s);
+        case 4: return launch_wave_t<4, true, false, 1, Q>(a, grid, s);
+        case 8: return launch_wave_t<8, true, false, 1, Q>(a, grid, s);
+        case 16: return launch_wave_t<16, true, false, 1, Q>(a, grid, s);
+        case 32: return launch_wave_t<32, true, false, 1, Q>(a, grid, s);
         default: return hipErrorInvalidValue;
         }
     }
     switch (Rt) {
-    case 1: return launch_wave_t<1, false, false, 1>(a, grid, s);
-    case 2: return launch_wave_t<2, false, false, 1>(a, grid, s);
-    case 4: return launch_wave_t<4, false, false, 1>(a, grid, s);
-    case 8: return launch_wave_t<8, false, false, 1>(a, grid, s);
-    case 16: return launch_wave_t<16, false, false, 1>(a, grid, s);
+    case 1: return launch_wave_t<1, false, false, 1, Q>(a, grid, s);
+    case 2: return launch_wave_t<2, false, false, 1, Q>(a, grid, s);
+    case 4: return launch_wave_t<4, false, false, 1, Q>(a, grid, s);
+    case 8: return launch_wave_t<8, false, false, 1, Q>(a, grid, s);
+    case 16: return launch_wave_t<16, false, false, 1, Q>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-int wave_max_blocks_per_cu(int Rt, int pmax, bool xg, bool dense, int tw, int nlds)
+template <bool Q>
+static int max_blocks_q(int Rt, int pmax, bool xg, bool dense, int tw, int nlds)
 {
     if (tw == 2 || tw == 4) {
         if (!xg || dense || Rt != 32) return 0;
-        return tw == 2 ? max_blocks_t<16, true, false, 2>(pmax, nlds) : max_blocks_t<8, true, false, 4>(pmax, nlds);
+        return tw == 2 ? max_blocks_t<16, true, false, 2, Q>(pmax, nlds) : max_blocks_t<8, true, false, 4, Q>(pmax, nlds);
     }
     if (tw != 1) return 0;
     if (dense) {
         if (!xg) return 0;
         switch (Rt) {
-        case 1: return max_blocks_t<1, true, true, 1>(pmax, nlds);
-        case 2: return max_blocks_t<2, true, true, 1>(pmax, nlds);
-        case 4: return max_blocks_t<4, true, true, 1>(pmax, nlds);
+        case 1: return max_blocks_t<1, true, true, 1, Q>(pmax, nlds);
+        case 2: return max_blocks_t<2, true, true, 1, Q>(pmax, nlds);
+        case 4: return max_blocks_t<4, true, true, 1, Q>(pmax, nlds);
         default: return 0;
         }
     }
     if (xg) {
         switch (Rt) {
-        case 1: return max_blocks_t<1, true, false, 1>(pmax, nlds);
-        case 2: return max_blocks_t<2, true, false, 1>(pmax, nlds);
-        case 4: return max_blocks_t<4, true, false, 1>(pmax, nlds);
-        case 8: return max_blocks_t<8, true, false, 1>(pmax, nlds);
-        case 16: return max_blocks_t<16, true, false, 1>(pmax, nlds);
-        case 32: return max_blocks_t<32, true, false, 1>(pmax, nlds);
+        case 1: return max_blocks_t<1, true, false, 1, Q>(pmax, nlds);
+        case 2: return max_blocks_t<2, true, false, 1, Q>(pmax, nlds);
+        case 4: return max_blocks_t<4, true, false, 1, Q>(pmax, nlds);
+        case 8: return max_blocks_t<8, true, false, 1, Q>(pmax, nlds);
+        case 16: return max_blocks_t<16, true, false, 1, Q>(pmax, nlds);
+        case 32: return max_blocks_t<32, true, false, 1, Q>(pmax, nlds);
         default: return 0;
         }
     }
     switch (Rt) {
-    case 1: return max_blocks_t<1, false, false, 1>(pmax, nlds);
-    case 2: return max_blocks_t<2, false, false, 1>(pmax, nlds);
-    case 4: return max_blocks_t<4, false, false, 1>(pmax, nlds);
-    case 8: return max_blocks_t<8, false, false, 1>(pmax, nlds);
-    case 16: return max_blocks_t<16, false, false, 1>(pmax, nlds);
+    case 1: return max_blocks_t<1, false, false, 1, Q>(pmax, nlds);
+    case 2: return max_blocks_t<2, false, false, 1, Q>(pmax, nlds);
+    case 4: return max_blocks_t<4, false, false, 1, Q>(pmax, nlds);
+    case 8: return max_blocks_t<8, false, false, 1, Q>(pmax, nlds);
+    case 16: return max_blocks_t<16, false, false, 1, Q>(pmax, nlds);
     default: return 0;
     }
+}
+
+hipError_t launch_wave(int Rt, bool xg, bool dense, int tw, bool quad, const SolveArgs &a, int grid, hipStream_t s)
+{
+    return quad ? launch_wave_q<true>(Rt, xg, dense, tw, a, grid, s) : launch_wave_q<false>(Rt, xg, dense, tw, a, grid, s);
+}
+
+int wave_max_blocks_per_cu(int Rt, int pmax, bool xg, bool dense, int tw, bool quad, int nlds)
+{
+    return quad ? max_blocks_q<true>(Rt, pmax, xg, dense, tw, nlds) : max_blocks_q<false>(Rt, pmax, xg, dense, tw, nlds);
 }
 
 // --------------------------------------------------------------------------
