@@ -496,6 +496,8 @@ def main():
                 mq = dict(plan=L.Plan.for_workload(wq, max_rounds=mr, flags=fl), d=L.to_device(wq),
                           n_out=wq.num_solves * wq.path_len)
                 entry["plain_kernel_1024"] = plain_comparison(L, torch, mq, wq, reps=3, parity=64)
+                mm = dict(plan=L.Plan.for_workload(wq, max_rounds=mr), d=mq["d"], n_out=mq["n_out"])
+                entry["plain_kernel_1024_median_sections"] = plain_comparison(L, torch, mm, wq, reps=3, parity=64)
             if cfg == "c2" and mr == 1:
                 gbs = ws.algorithmic_bytes() / (s["ms"] / 1e3) / 1e9
                 entry["hbm"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",

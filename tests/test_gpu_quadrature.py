@@ -108,3 +108,45 @@ def test_quadrature_stuck_instance(torch):
     assert out[1]["status"][0] in OK
     assert abs(out[1]["obj"][0] - g["f_opt"]) <= 1e-5 * g["f_opt"]
     np.testing.assert_allclose(out[1]["b"], g["b_opt"], rtol=1e-4, atol=1e-4)
+
+
+@pytest.mark.parametrize("kernel", ["wave", "plain"])
+def test_quadrature_edge_shapes(torch, kernel):
+    """Shapes across every register-slot count and ragged tail (n = 1 ..
+    2048, p = 1 .. 32), with the quadrature sections."""
+    from test_gpu_parity import _pack, assert_parity, gpu_solve
+    rng = np.random.default_rng(13)
+    blocks, lams = [], []
+    for n in [1, 2, 5, 63, 64, 65, 129, 257, 513, 1025, 2048]:
+        for p in [1, 2, 17, 32]:
+            X = rng.standard_normal((n, p))
+            y = X[:, : min(p, 3)] @ rng.uniform(-3, 3, min(p, 3)) + rng.laplace(0, 1, n)
+            blocks.append((X, y))
+            lams.append(float(10 ** rng.uniform(-2, 1)))
+    w = _pack(blocks, lams)
+    plan, g = gpu_solve(torch, w, plain=(kernel == "plain"), flags=QF)
+    assert_parity(w, g, oracle_ref(w), min_strict=0.0)
+
+
+@pytest.mark.parametrize("kernel", ["wave", "plain"])
+def test_quadrature_degenerate_inputs(torch, kernel):
+    """y = 0, a zero column (no kinks on that axis), duplicated rows (equal
+    kinks), lambda above lambda_max and lambda = 0."""
+    from test_gpu_parity import _pack, gpu_solve
+    rng = np.random.default_rng(4)
+    n, p = 100, 6
+    X = rng.standard_normal((n, p))
+    y = X @ np.array([1.0, 0, -2, 0, 0, 0.5]) + rng.laplace(0, 1, n)
+    Xz = X.copy()
+    Xz[:, 3] = 0.0
+    Xd = np.repeat(X[:50], 2, axis=0)
+    yd = np.repeat(y[:50], 2)
+    blocks = [(X, np.zeros(n)), (Xz, y), (Xd, yd), (X, y), (X, y)]
+    lmax = float(np.max(np.abs(X.astype(np.float32).astype(np.float64).T @ np.sign(y))))
+    w = _pack(blocks, [1.0, 1.0, 0.5, 1.5 * lmax, 0.0])
+    plan, g = gpu_solve(torch, w, plain=(kernel == "plain"), flags=QF)
+    fails, st = compare(w, g, oracle_ref(w))
+    assert not fails, fails
+    assert g["obj"][0] == 0.0 and np.all(g["b"][:p] == 0)
+    assert g["b"][p * 1 + 3] == 0.0
+    assert np.all(g["b"][3 * p: 4 * p] == 0) and g["active"][3] == 0

@@ -58,6 +58,20 @@ def test_noalloc_matches_plan_solve_twice(torch):
         assert ncert >= 0.9 * w.num_solves * w.path_len, ncert
 
 
+def test_noalloc_quadrature_variant(torch):
+    """The quadrature variant through the allocation-free entry point: the
+    same outputs as the plan-based solve with the same flag."""
+    w = W.config1(num_problems=64, num_lambda=2, as_path=True)
+    n, p = w.n(0), int(w.p[0])
+    d = L.to_device(w)
+    plan = L.Plan.for_workload(w, flags=L.FLAG_QUADRATURE)
+    ref = to_numpy(plan.solve(d["X"], d["y"], d["lam"]))
+    got = to_numpy(L.solve_uniform_noalloc(d["X"], d["y"], d["lam"], w.num_problems, n, p, w.path_len,
+                                           flags=L.FLAG_QUADRATURE))
+    torch.cuda.synchronize()
+    assert agree(w, ref, got) >= 0.9 * w.num_solves * w.path_len
+
+
 def test_noalloc_rejects_out_of_limits(torch):
     dev = "cuda"
     X = torch.zeros(2 * 1100 * 4, dtype=torch.float32, device=dev)
