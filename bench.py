@@ -179,10 +179,17 @@ def measure(L, torch, w, steps, warmup, parity_solves, autotune=False, **opts):
     fails, pst = compare(w, g, oracle_ref(w, solves=sample), solves=sample)
     log(f"{w.name}: parity {'ok' if not fails else 'FAILED'} {pst}")
     status = {L.STATUS_NAMES[s]: int(c) for s, c in zip(*np.unique(g["status"], return_counts=True))}
+    # which stage certified each output: no probe and no pivot = the first
+    # descent and its vertex; probes but no pivot = the chop; pivots = the
+    # finisher (the counters are per output)
+    cert = np.isin(g["status"], [L.CERTIFIED, L.NONUNIQUE])
+    stages = {"descent_and_snap": int(np.sum(cert & (it[:, 2] == 0) & (it[:, 3] == 0))),
+              "chop": int(np.sum(cert & (it[:, 2] > 0) & (it[:, 3] == 0))),
+              "finisher": int(np.sum(cert & (it[:, 3] > 0))), "uncertified": int(np.sum(~cert))}
     every_ok = bool(np.all(np.isfinite(g["obj"])) and np.all(g["obj"] >= 0))
     return dict(plan=plan, d=d, out=out, g=g, ms=ms, solves_per_s=n_out / (ms / 1e3), n_out=n_out,
                 row_updates=float(upd_rows.sum()), buckets=per_bucket, parity_ok=not fails and every_ok,
-                parity=pst, fails=fails, status=status,
+                parity=pst, fails=fails, status=status, stages=stages,
                 iters_mean={"sweeps": float(it[:, 0].mean()), "updates": float(it[:, 1].mean()),
                             "probes": float(it[:, 2].mean()), "pivots": float(it[:, 3].mean())},
                 describe=plan.describe())
@@ -396,7 +403,8 @@ def secondary_entry(w, s, mr, fl):
             "solves_per_s": s["solves_per_s"],
             "ms_per_step": s["ms"], "parity_ok": s["parity_ok"], "max_rel_f": s["parity"]["max_rel_f"],
             "strict_of_unique": [s["parity"]["strict"], s["parity"]["unique"]],
-            "iters_mean": s["iters_mean"], "status": s["status"], "buckets": s["buckets"]}
+            "iters_mean": s["iters_mean"], "status": s["status"], "certified_by_stage": s["stages"],
+            "buckets": s["buckets"]}
 
 
 def main():
@@ -532,6 +540,7 @@ def main():
         "parity": {"ok": m["parity_ok"], "sample_solves": int(len(psolves)), **m["parity"],
                    "first_failures": [str(f) for f in m["fails"][:3]]},
         "status": m["status"],
+        "certified_by_stage": m["stages"],
         "iters_mean": m["iters_mean"],
         "buckets": m["buckets"],
         "secondary": secondary,

@@ -1537,10 +1537,14 @@ LADL_INL void solve_item(Wave<R, XG, TW> &w, const SolveArgs &a, int s)
             if (done) {
                 bv = (l < p) ? w.vt[l] : 0.f;
                 zcount = vs;
-            } else if (!snap) {
-                status = ST_MAXITER;
+                // f at the certified vertex, summed in fp64 from its fp64
+                // residuals when it was evaluated (b is that vertex rounded
+                // to fp32, which moves f by about 1e-7 relative)
+                fout = (float)w.fv64;
+            } else {
+                if (!snap) status = ST_MAXITER;
+                fout = objective64(w, bv);
             }
-            fout = objective64(w, bv);
         }
         // outputs (first wave of the team)
         uint64_t act = ballot(l < p && bv != 0.f);
