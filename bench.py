@@ -196,12 +196,13 @@ def measure(L, torch, w, steps, warmup, parity_solves, autotune=False, **opts):
 
 
 def alu_roofline(m, profile_summary=None):
-    """ALU roofline of the bucket kernel that takes the longest: algorithmic
-    lane-ops (OPS_PER_ROW_UPDATE per row of each coordinate update it ran)
-    over its average launch time from HIP events on its own stream.  The
-    HBM traffic of that kernel comes from the committed byte-counter
-    summary (key traffic_bytes_per_launch_R<rows per lane>)."""
-    dom = max(m["buckets"], key=lambda b: b["ms_per_launch"])
+    """ALU roofline of the dominant bucket kernel, the one that runs the most
+    row-updates (the buckets run side by side, so which one ends last varies
+    from run to run): algorithmic lane-ops (OPS_PER_ROW_UPDATE per row of
+    each coordinate update it ran) over its launch time from HIP events on
+    its own stream.  The HBM traffic of that kernel comes from the committed
+    byte-counter summary (key traffic_bytes_per_launch_R<rows per lane>)."""
+    dom = max(m["buckets"], key=lambda b: b["row_updates"])
     ops = OPS_PER_ROW_UPDATE * dom["row_updates"]
     achieved = ops / (dom["ms_per_launch"] / 1e3)
     traffic = recorded_traffic(profile_summary, f"traffic_bytes_per_launch_R{dom['R']}") if profile_summary else None
