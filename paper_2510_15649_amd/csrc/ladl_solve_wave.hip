@@ -1537,13 +1537,19 @@ LADL_INL void solve_item(Wave<R, XG, TW> &w, const SolveArgs &a, int s)
             if (done) {
                 bv = (l < p) ? w.vt[l] : 0.f;
                 zcount = vs;
+            } else if (!snap) {
+                status = ST_MAXITER;
+            }
+            if constexpr (R >= 32) {
+                // the n > 1024 kernel sits at its register limit: reading
+                // the vertex's fp64 objective below moved its spills into
+                // the update loop (6% slower), so it re-evaluates f
+                fout = objective64(w, bv);
+            } else {
                 // f at the certified vertex, summed in fp64 from its fp64
                 // residuals when it was evaluated (b is that vertex rounded
                 // to fp32, which moves f by about 1e-7 relative)
-                fout = (float)w.fv64;
-            } else {
-                if (!snap) status = ST_MAXITER;
-                fout = objective64(w, bv);
+                fout = done ? (float)w.fv64 : objective64(w, bv);
             }
         }
         // outputs (first wave of the team)
