@@ -150,3 +150,46 @@ def test_quadrature_degenerate_inputs(torch, kernel):
     assert g["obj"][0] == 0.0 and np.all(g["b"][:p] == 0)
     assert g["b"][p * 1 + 3] == 0.0
     assert np.all(g["b"][3 * p: 4 * p] == 0) and g["active"][3] == 0
+
+
+def test_quadrature_full_c2_sampled(torch):
+    """All 4096 ragged row subsets with quadrature sections in one plan: every
+    output certified, 64 seeded solves against the oracle."""
+    from test_gpu_full_sizes import check_every_output
+    w = W.config2()
+    print(f"[gpu] quadrature sections, full c2 solves={w.num_solves}", flush=True)
+    plan = L.Plan.for_workload(w, flags=QF)
+    d = L.to_device(w)
+    g = to_numpy(plan.solve(d["X"], d["y"], d["lam"]))
+    torch.cuda.synchronize()
+    check_every_output(w, g)
+    sample = np.sort(np.random.default_rng(22).choice(w.num_solves, size=64, replace=False))
+    fails, st = compare(w, g, oracle_ref(w, solves=sample), solves=sample)
+    print(st, flush=True)
+    assert not fails, fails[:5]
+
+
+def test_quadrature_path_graph_and_backward(torch):
+    """A 4-step lambda path of ragged problems with quadrature sections: the
+    HIP graph path (one launch per step) equals the in-kernel path bit for
+    bit, and the backward at the last step matches the oracle's vertex-form
+    gradient where the optimum is strictly unique."""
+    from test_gpu_backward_path import check_backward
+    w = W.config4(problems=range(12), path_len=4)
+    d = L.to_device(w)
+    plan = L.Plan.for_workload(w, flags=QF)
+    ref_out = plan.solve(d["X"], d["y"], d["lam"])
+    ref = to_numpy(ref_out)
+    out = plan.alloc_outputs()
+    graph = plan.graph(d["X"], d["y"], d["lam"], out)
+    graph.launch()
+    torch.cuda.synchronize()
+    got = to_numpy(out)
+    for key in ("b", "obj", "active", "zero_rows", "status"):
+        assert np.array_equal(got[key], ref[key]), key
+    g = torch.from_numpy(w.grad_b).cuda()
+    gy, gX = plan.backward(d["X"], ref_out, g, step=w.path_len - 1)
+    torch.cuda.synchronize()
+    oref = oracle_ref(w)
+    checked = check_backward(w, ref, gy.cpu().numpy(), gX.cpu().numpy(), oref, w.grad_b, w.path_len - 1, 1)
+    print(f"gradients checked against the oracle: {checked}", flush=True)
