@@ -11,9 +11,12 @@
  *
  * Parity status of each entry point (what pins it is listed in the tests):
  *   orc_objective, orc_weighted_median, orc_coord_update, orc_brute_force,
- *   orc_lp_simplex, orc_certify, orc_solve (its result), orc_backward:
+ *   orc_lp_simplex, orc_certify, orc_solve (its result, with either section
+ *   search), orc_backward, orc_solve_batch:
  *       pinned (brute force on tiny inputs, an independent LP solver,
- *       closed forms, LP duality, finite differences).
+ *       closed forms, LP duality, finite differences, single solves).
+ *   orc_quadrature_update: pinned against the section minimum found by
+ *       brute force over the section's kinks, to the search's bracket.
  *   The intermediate iterates of orc_solve's paper-method stages (the
  *   sequence of CCD sweeps and ternary probes) are "parity unpinned": the
  *   paper gives the search only as an outline (Sections 3.5-3.6), so only
