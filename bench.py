@@ -1,7 +1,8 @@
 """Benchmark: batched LAD-LASSO solves/s on one MI355X.
 
 One step = one forward pass of the whole solve path (cyclical coordinate
-descent with exact weighted-median coordinate updates, ternary chop along
+descent with exact weighted-median coordinate updates, or with the quadrature
+search of each section under --quadrature, ternary chop along
 the locus of axis-wise minima, vertex snap and optimality certificate,
 edge-descent finisher) over one batch.  The headline workload is the large
 ragged batch: 65536 problems, n ~ U[32, 2048], p ~ U[4, 32], each solved
@@ -10,7 +11,9 @@ bucket (2,097,152 solves per step).  Inputs are resident in HBM before
 timing starts.  Prints one JSON line.
 
 Secondary lines: 512 problems x 16 lambdas with the plain one-thread-per-
-solve kernel beside the wave kernel (the speed-up claim), the 4096 row
+solve kernel beside the wave kernel (the speed-up claim), the same
+problems without the chop, with golden sections and with the quadrature
+variant (on both kernels), the 4096 row
 subsets of one correlated dataset (achieved HBM GB/s against the peak), the
 differentiation workload with its backward, the ragged batch's lambda path
 as a HIP graph and its backward against the HBM roofline, K-fold
