@@ -12,7 +12,7 @@ timing starts.  Prints one JSON line.
 
 Secondary lines: 512 problems x 16 lambdas with the plain one-thread-per-
 solve kernel beside the wave kernel (the speed-up claim), the same
-problems without the chop, with golden sections and with the quadrature
+problems without the chop, with the bracket cut in thirds and with the quadrature
 variant (on both kernels), the 4096 row
 subsets of one correlated dataset (achieved HBM GB/s against the peak), the
 differentiation workload with its backward, the ragged batch's lambda path
@@ -277,7 +277,7 @@ def cpu_baseline(L, w, seed=99, target_s=8.0):
     d_opt = L.default_options()
     opts = dict(max_rounds=int(d_opt.max_rounds), tol_f=float(d_opt.tol_f), tol_s=float(d_opt.tol_s),
                 max_sweeps=int(d_opt.max_sweeps), max_ternary=int(d_opt.max_ternary),
-                chop_range=float(d_opt.chop_range))
+                chop_range=float(d_opt.chop_range), golden=int(bool(d_opt.flags & L.FLAG_GOLDEN)))
     rng = np.random.default_rng(seed)
     perm = rng.permutation(w.num_solves)
     k = min(w.num_solves, max(threads, 8))
@@ -418,7 +418,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c4")
     ap.add_argument("--max-rounds", type=int, default=1)
-    ap.add_argument("--golden", action="store_true")
+    ap.add_argument("--thirds", action="store_true",
+                    help="cut the chop's bracket in thirds instead of golden sections (the library default)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--quadrature", action="store_true",
                     help="the quadrature variant: 1-D sections minimised by a quadrature search of their values")
@@ -454,7 +455,9 @@ def main():
         return
     log(f"generating workload {args.config}")
     w = make_workload(args.config)
-    flags = (L.FLAG_GOLDEN if args.golden else 0) | (L.FLAG_QUADRATURE if args.quadrature else 0)
+    default_flags = int(L.default_options().flags)
+    flags = (default_flags & ~L.FLAG_GOLDEN if args.thirds else default_flags) | \
+        (L.FLAG_QUADRATURE if args.quadrature else 0)
     if args.config in ("c4", "c4s"):
         psolves = c4_parity_solves(w, n_uniform=args.parity_sample)
     else:
@@ -463,7 +466,7 @@ def main():
     m = measure(L, torch, w, args.steps, args.warmup, psolves, args.autotune, max_rounds=args.max_rounds,
                 flags=flags, team=args.team)
     ms = m["ms"]
-    default_run = args.max_rounds == 1 and flags == 0 and not args.autotune and args.team == 0
+    default_run = args.max_rounds == 1 and flags == default_flags and not args.autotune and args.team == 0
     summary = {"c4": "k_wave_c4_full_hbm_bytes.md", "c2": "k_wave_c2_kernel_stats.md",
                "c1": "k_wave_c1_hbm_bytes.md"}.get(args.config) if default_run else None
     roof = alu_roofline(m, summary)
@@ -484,8 +487,9 @@ def main():
     secondary = []
     plain = None
     if not args.no_secondary:
-        for cfg, mr, fl in [("c1", 1, 0), ("c1", 0, 0), ("c1", 1, L.FLAG_GOLDEN), ("c1", 1, L.FLAG_QUADRATURE),
-                            ("c2", 1, 0), ("c2", 0, 0), ("c3", 1, 0)]:
+        G, Q = L.FLAG_GOLDEN, L.FLAG_QUADRATURE
+        for cfg, mr, fl in [("c1", 1, G), ("c1", 0, G), ("c1", 1, 0), ("c1", 1, G | Q),
+                            ("c2", 1, G), ("c2", 0, G), ("c3", 1, G)]:
             if cfg == args.config and mr == args.max_rounds and fl == flags:
                 continue
             log(f"generating workload {cfg}")
@@ -494,13 +498,13 @@ def main():
             samp = np.sort(rng.choice(ws.num_solves, size=min(128, ws.num_solves), replace=False))
             s = measure(L, torch, ws, 3, 1, samp, args.autotune, max_rounds=mr, flags=fl)
             entry = secondary_entry(ws, s, mr, fl)
-            if cfg == "c1" and mr == 1 and fl == 0:
+            if cfg == "c1" and mr == 1 and fl == G:
                 log("plain one-thread-per-solve kernel, median of 10 launches")
                 plain = plain_comparison(L, torch, s, ws)
                 entry["plain_kernel"] = plain
                 entry["vs_plain"] = s["solves_per_s"] / plain["value"]
                 entry["roofline"] = alu_roofline(s, "k_wave_c1_hbm_bytes.md")
-            if cfg == "c1" and fl == L.FLAG_QUADRATURE:
+            if cfg == "c1" and fl & Q:
                 # the paper's one-thread-per-problem design with quadrature
                 # sections, on the first 64 of the 512 problems (1024 solves)
                 log("plain kernel with quadrature sections, 1024 solves, median of 3 launches")
@@ -531,7 +535,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic (seeded generator, no dataset)",
         "config": {"workload": w.name, "solves_per_step": m["n_out"], "max_rounds": args.max_rounds,
-                   "golden": bool(args.golden), "quadrature": bool(args.quadrature),
+                   "golden": bool(flags & L.FLAG_GOLDEN), "quadrature": bool(args.quadrature),
                    "autotune": bool(args.autotune), "team": args.team,
                    "parallelism": "1 GPU, one wavefront per solve, buckets side by side",
                    "path_len": w.path_len, "graph_ms_per_step": graph_ms, "graph_equals_in_kernel": graph_same},

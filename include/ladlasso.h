@@ -71,8 +71,13 @@ enum {
 
 /* option flags */
 enum {
-    LADL_FLAG_GOLDEN = 1,       /* golden-section instead of thirds in the
-                                   ternary chop (same limit, fewer probes)   */
+    LADL_FLAG_GOLDEN = 1,       /* golden-section split of the ternary
+                                   chop's bracket instead of thirds: the same
+                                   search (same bracket invariant and limit)
+                                   with one interior probe carried over per
+                                   step, so about half the probes; set in
+                                   the default options (clear it for
+                                   thirds)                                   */
     LADL_FLAG_NO_FINISHER = 2,  /* stop after the paper's stages             */
     LADL_FLAG_NO_SNAP = 4,      /* no vertex snap/certificate: b is the last
                                    coordinate-descent point, status MAXITER  */
@@ -106,7 +111,7 @@ typedef struct {
     int32_t max_rounds;  /* chop rounds, each on the next axis: 0 none,
                             -1 one per axis                   (default 1)     */
     int32_t max_pivots;  /* finisher pivots; <= 0 means 4p + 32 (default 0)   */
-    int32_t flags;       /* LADL_FLAG_*                       (default 0)     */
+    int32_t flags;       /* LADL_FLAG_*          (default LADL_FLAG_GOLDEN)   */
     int32_t schedule;    /* -1: per bucket, X in LDS when it fits 40 KB per
                             wave, else in an HBM workspace, and for
                             n <= 256 with more than two grids' worth of

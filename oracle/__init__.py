@@ -27,7 +27,7 @@ class Opts(C.Structure):
     _fields_ = [("tol_f", C.c_double), ("tol_s", C.c_double), ("lambda_min", C.c_double),
                 ("max_sweeps", C.c_int), ("max_ternary", C.c_int), ("max_rounds", C.c_int),
                 ("max_pivots", C.c_int), ("use_finisher", C.c_int), ("chop_range", C.c_double),
-                ("section", C.c_int), ("tol_q", C.c_double)]
+                ("section", C.c_int), ("tol_q", C.c_double), ("golden", C.c_int)]
 
 
 class Prob(C.Structure):

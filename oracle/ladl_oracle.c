@@ -38,6 +38,7 @@ void orc_default_opts(orc_opts *o)
     o->use_finisher = 1;
     o->chop_range = 1.0 / 32.0;
     o->section = ORC_SECTION_MEDIAN;
+    o->golden = 0;
     o->tol_q = 1e-13;
 }
 
@@ -704,7 +705,8 @@ int orc_certify(const orc_prob *P, double lambda, double *b, double *u, orc_info
 /* it holds the minimum, Section 3.6) is doubled outward while an end point */
 /* is lower than the centre, clamped to                                       */
 /* |b_k| <= ||y||_1 / lambda (any minimiser has lambda ||b||_1 <= f(0)).      */
-/* The range is then cut in thirds; the best probe is kept.                  */
+/* The range is then cut in thirds (or golden sections); the best probe is  */
+/* kept.                                                                     */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -778,14 +780,47 @@ static void ternary(otern *T)
     }
     (void)Flo;
     (void)Fhi;
+    if (!T->o->golden) {
+        for (int it = 0; it < T->o->max_ternary; ++it) {
+            if (hi - lo <= T->o->tol_s * (1.0 + fabs(lo) + fabs(hi))) break;
+            double m1 = lo + (hi - lo) / 3.0, m2 = hi - (hi - lo) / 3.0;
+            double F1 = probe(T, m1), F2 = probe(T, m2);
+            if (F1 < F2)
+                hi = m2;
+            else
+                lo = m1;
+        }
+        return;
+    }
+    /* golden sections: the same search with interior points at the golden
+     * ratio, so the interior point that survives a step is one of the next
+     * step's two points and only one new probe is needed per step */
+    const double g = 0.5 * (3.0 - sqrt(5.0));
+    double m1 = 0.0, m2 = 0.0, F1 = 0.0, F2 = 0.0;
+    int have1 = 0, have2 = 0;
     for (int it = 0; it < T->o->max_ternary; ++it) {
         if (hi - lo <= T->o->tol_s * (1.0 + fabs(lo) + fabs(hi))) break;
-        double m1 = lo + (hi - lo) / 3.0, m2 = hi - (hi - lo) / 3.0;
-        double F1 = probe(T, m1), F2 = probe(T, m2);
-        if (F1 < F2)
+        if (!have1) {
+            m1 = lo + g * (hi - lo);
+            F1 = probe(T, m1);
+            have1 = 1;
+        }
+        if (!have2) {
+            m2 = hi - g * (hi - lo);
+            F2 = probe(T, m2);
+            have2 = 1;
+        }
+        if (F1 < F2) {
             hi = m2;
-        else
+            m2 = m1;
+            F2 = F1;
+            have1 = 0;
+        } else {
             lo = m1;
+            m1 = m2;
+            F1 = F2;
+            have2 = 0;
+        }
     }
 }
 

@@ -51,6 +51,7 @@ typedef struct {
     double chop_range; /* initial chop half-width, a fraction of max(1, |b_k|)     */
     int section;       /* 1-D section minimiser: ORC_SECTION_*                     */
     double tol_q;      /* quadrature bracket stops at hi-lo <= tol_q*(1+|lo|+|hi|) */
+    int golden;        /* 1: golden-section split of the chop's bracket, else thirds */
 } orc_opts;
 
 /* how CCD minimises each 1-D section */

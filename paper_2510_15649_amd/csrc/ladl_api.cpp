@@ -135,7 +135,7 @@ void ladl_default_options(ladl_options *o)
     o->max_ternary = 48;
     o->max_rounds = 1;
     o->max_pivots = 0;
-    o->flags = 0;
+    o->flags = LADL_FLAG_GOLDEN;
     o->schedule = -1;
     o->chop_range = 0.03125f;
     o->team = 0;

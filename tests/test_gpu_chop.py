@@ -56,15 +56,19 @@ def exact_min(w):
     return f
 
 
+SPLITS = pytest.mark.parametrize("split", [0, L.FLAG_GOLDEN], ids=["thirds", "golden"])
+
+
+@SPLITS
 @pytest.mark.parametrize("kernel", ["wave", "plain"])
-def test_p2_chop_alone_reaches_the_minimum(torch, kernel):
+def test_p2_chop_alone_reaches_the_minimum(torch, kernel, split):
     w = p2_workload()
-    print(f"[gpu] chop without finisher, {w.name}, {kernel}", flush=True)
+    print(f"[gpu] chop without finisher, {w.name}, {kernel}, split {split}", flush=True)
     fstar = exact_min(w)
     d = L.to_device(w)
     res = {}
     for rounds in (0, 1):
-        plan = L.Plan.for_workload(w, flags=L.FLAG_NO_FINISHER, max_rounds=rounds)
+        plan = L.Plan.for_workload(w, flags=L.FLAG_NO_FINISHER | split, max_rounds=rounds)
         fn = plan.solve if kernel == "wave" else plan.solve_plain
         res[rounds] = to_numpy(fn(d["X"], d["y"], d["lam"]))
         torch.cuda.synchronize()
@@ -96,8 +100,9 @@ def test_p2_chop_alone_reaches_the_minimum(torch, kernel):
           f"max rel error with it {np.max(rel1):.2e}", flush=True)
 
 
+@SPLITS
 @pytest.mark.parametrize("kernel", ["wave", "plain"])
-def test_stuck_instance_escaped_by_the_chop(torch, kernel):
+def test_stuck_instance_escaped_by_the_chop(torch, kernel, split):
     """The golden stuck instance: coordinate descent stops at an axis-wise
     minimum 0.55 above the optimum, and its nearest vertex does not certify;
     the chop reaches the optimum."""
@@ -107,7 +112,7 @@ def test_stuck_instance_escaped_by_the_chop(torch, kernel):
     d = L.to_device(w)
     out = {}
     for rounds in (0, 1):
-        plan = L.Plan.for_workload(w, flags=L.FLAG_NO_FINISHER, max_rounds=rounds)
+        plan = L.Plan.for_workload(w, flags=L.FLAG_NO_FINISHER | split, max_rounds=rounds)
         fn = plan.solve if kernel == "wave" else plan.solve_plain
         out[rounds] = to_numpy(fn(d["X"], d["y"], d["lam"]))
         torch.cuda.synchronize()

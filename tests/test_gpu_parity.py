@@ -71,6 +71,7 @@ def test_c2_subset(torch, kernel):
 
 
 @pytest.mark.parametrize("opts", [dict(max_rounds=0), dict(max_rounds=1, flags=L.FLAG_GOLDEN),
+                                  dict(max_rounds=1, flags=0),
                                   dict(max_rounds=2, tol_s=1e-3), dict(chop_range=1.0, max_sweeps=64),
                                   dict(chop_range=1e-3, max_sweeps=1), dict(max_rounds=-1, schedule=0),
                                   dict(schedule=1)])
