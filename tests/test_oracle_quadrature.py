@@ -178,3 +178,22 @@ def test_quadrature_batch_reaches_the_same_optima():
     both = (rq["cert"] == 2) & (rm["cert"] == 2)
     assert np.array_equal(rq["smask"][both], rm["smask"][both])
     assert np.array_equal(rq["zrows"][both], rm["zrows"][both])
+
+
+def test_ccd_ends_at_an_axiswise_minimum():
+    """Both section searches: coordinate descent run to convergence stops at a
+    point where every coordinate minimises its own section (Section 3.3's
+    stopping point, an axis-wise minimum), checked by brute force over each
+    section's kinks in numpy."""
+    rng = np.random.default_rng(17)
+    for it in range(40):
+        n, p = int(rng.integers(5, 50)), int(rng.integers(2, 6))
+        X = rng.standard_normal((n, p))
+        y = X @ rng.uniform(-2, 2, p) + rng.laplace(0, 1, n)
+        lam = float(10 ** rng.uniform(-2, 1))
+        for opts in (dict(), Q):
+            b, f, sweeps = O.ccd(X, y, lam, **opts)
+            assert sweeps < 1000
+            for j in range(p):
+                gmin, mlo, mhi, kinks, g = section_minimum(X, y, lam, b, j)
+                assert g(b[j]) <= gmin + 1e-9 * (1 + gmin), (it, opts, j, g(b[j]), gmin)
