@@ -590,11 +590,11 @@ LADL_INL bool coord_update(Wave<R, XG, TW> &w, float (&r)[R], float &bv, int j, 
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const float rr = r[k], ax = fabsf(x[k]);
-        const bool z = (rr == 0.f);
-        const bool neg = (fbits(rr) ^ fbits(x[k])) < 0;
-        const float wz = z ? ax : 0.f;
-        at += wz;
-        bel += neg ? ax - wz : 0.f;
+        // r_i x_ij < 0: the kink lies below b_j (a zero residual gives a
+        // zero product: that kink is at b_j)
+        const bool neg = rr * x[k] < 0.f;
+        at += (rr == 0.f) ? ax : 0.f;
+        bel += neg ? ax : 0.f;
     }
     const float bj = rdlane(bv, j);
     tsum2(w.tm, bel, at);
