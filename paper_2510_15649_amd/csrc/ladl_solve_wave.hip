@@ -700,11 +700,13 @@ LADL_INL bool coord_update(Wave<R, XG, TW> &w, float (&r)[R], float &bv, int j, 
     }
     const float d = nb - bj;
     if (d == 0.f || !__builtin_isfinite(d)) return false;
-    const bool own = !virt && w.wv == owave && l == olane;
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const float rn = fmaf(-x[k], d, r[k]);
-        r[k] = (own && k == oslot) ? 0.f : rn; // the median row is now on its hyperplane
+    for (int k = 0; k < R; ++k) r[k] = fmaf(-x[k], d, r[k]);
+    // the median row is now on its hyperplane: its residual is exactly zero
+    // (one register slot of one lane, the slot index uniform)
+    if (!virt && w.wv == owave) {
+        const int os = uni(oslot);
+        r[os] = (l == olane) ? 0.f : r[os];
     }
     bv = (l == j) ? nb : bv;
     return true;
