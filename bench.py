@@ -409,6 +409,12 @@ def measure_brute(L, torch, steps=3, sample=16):
     cd_vs_brute = float(np.max(np.abs(f_cd - obj) / np.maximum(1.0, np.abs(obj))))
     st_cd = out_s["status"].cpu().numpy()
     pms, _ = median_ms(torch, lambda: plan.solve_plain(d["X"], d["y"], d["lam"], stream=stream), 3, stream)
+    # the tile schedule (4 problems per wavefront for the descent and chop)
+    plan_t = L.Plan.for_workload(w, tile=2)
+    out_t = plan_t.solve(d["X"], d["y"], d["lam"], stream=stream)
+    tms, _ = median_ms(torch, lambda: plan_t.solve(d["X"], d["y"], d["lam"], out=out_t, stream=stream), steps, stream)
+    f_t = out_t["obj"].cpu().numpy().astype(np.float64)
+    st_t = out_t["status"].cpu().numpy()
     return {"workload": f"vertex enumeration, {w.name}", "ms_per_step": ms,
             "solves_per_s": w.num_solves / (ms / 1e3), "candidate_vertices_per_step": float(cand.sum()),
             "roofline": {"bound": "alu", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s (fp64)",
@@ -419,7 +425,11 @@ def measure_brute(L, torch, steps=3, sample=16):
                                    "max_rel_f_vs_enumeration": cd_vs_brute,
                                    "certified": int(np.sum(np.isin(st_cd, [L.CERTIFIED, L.NONUNIQUE])))},
             "coordinate_descent_plain_kernel": {"ms_per_step": pms, "solves_per_s": w.num_solves / (pms / 1e3),
-                                                "launches": 3}}
+                                                "launches": 3},
+            "coordinate_descent_tile_schedule": {
+                "ms_per_step": tms, "solves_per_s": w.num_solves / (tms / 1e3), "tile": plan_t.tiles()[0],
+                "max_rel_f_vs_enumeration": float(np.max(np.abs(f_t - obj) / np.maximum(1.0, np.abs(obj)))),
+                "certified": int(np.sum(np.isin(st_t, [L.CERTIFIED, L.NONUNIQUE])))}}
 
 
 def secondary_entry(w, s, mr, fl):

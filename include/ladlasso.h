@@ -135,6 +135,21 @@ typedef struct {
                             wavefronts of one workgroup, the rows split
                             between them; smaller problems always take one
                             wavefront                          (default 0)    */
+    int32_t tile;        /* tile schedule for problems of n <= 64: 0 the
+                            library's choice (off unless ladl_autotune
+                            measures it faster), 1 off, 2 on.  On, the
+                            coordinate descent (Sections 3.3-3.4) of each
+                            path step first runs with 4 problems per
+                            wavefront (n <= 32, segments of 16 lanes) or 2
+                            (n <= 64, 32 lanes) and stops at its first
+                            axis-wise minimum; the wavefront kernel then
+                            starts each step from that point and runs the
+                            rest of the solve.  Results are certified as
+                            without it, but may be a different optimal
+                            vertex where the optimum is not unique, and
+                            `iters` counts the wavefront stage's work only.
+                            Excludes LADL_FLAG_QUADRATURE (EINVAL with 2;
+                            never chosen with 0)               (default 0)    */
 } ladl_options;
 
 /*
@@ -269,8 +284,9 @@ int ladl_graph_destroy(ladl_graph_t graph);
  * several times on `stream`, synchronously) and keep the fastest per
  * bucket in the plan: X resident in LDS, X in the HBM workspace, (for
  * n <= 256) X in the HBM workspace with the 4-waves-per-SIMD kernel
- * variant, and (for n > 1024) teams of 2 or 4 wavefronts per solve, for
- * the buckets where more than one exists.  The paper leaves the mapping of
+ * variant, (for n > 1024) teams of 2 or 4 wavefronts per solve, and (for
+ * n <= 64, options.tile = 0) each of these with the tile stage in front,
+ * for the buckets where more than one exists.  The paper leaves the mapping of
  * problems onto the hardware to the application (coarse parallelism,
  * Abstract and Section 5); this picks it by measurement.  The choice is
  * cached in the file named by the environment variable LADL_TUNE_CACHE (if
@@ -409,8 +425,9 @@ int ladl_cv_run(ladl_cv_t cv, const float *X, const float *y, const float *lambd
  * row-major X block at X + k*n*p, its y at y + k*n), solve k runs problem
  * k along its lambda path lambda[k*path_len .. (k+1)*path_len), and the
  * outputs are laid out as ladl_solve_f32 lays them out (b of (k, t) at
- * b + (k*path_len + t)*p).  opt may be NULL (defaults); its schedule field
- * is ignored: X is always held in LDS.
+ * b + (k*path_len + t)*p).  opt may be NULL (defaults); it is validated as
+ * for a plan, and its schedule, team and tile fields are then ignored: one
+ * wavefront per problem, X always held in LDS.
  *
  * Nothing is allocated and no library routine that allocates is called:
  * the work-queue counter and the per-problem metadata live in a fixed

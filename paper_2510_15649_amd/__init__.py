@@ -37,7 +37,7 @@ class Options(C.Structure):
     _fields_ = [("tol_f", C.c_float), ("tol_s", C.c_float), ("lambda_min", C.c_float),
                 ("max_sweeps", C.c_int32), ("max_ternary", C.c_int32), ("max_rounds", C.c_int32),
                 ("max_pivots", C.c_int32), ("flags", C.c_int32), ("schedule", C.c_int32),
-                ("chop_range", C.c_float), ("team", C.c_int32)]
+                ("chop_range", C.c_float), ("team", C.c_int32), ("tile", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -383,6 +383,12 @@ class Plan:
         import re
         return [tuple(int(v) for v in m.groups()) for m in
                 re.finditer(r"bucket R=(\d+) \(n<=(\d+)\) pmax=(\d+) solves=(\d+)", self.describe())]
+
+    def tiles(self):
+        """Tile schedule of each bucket, in describe() order: "SxR" (segments
+        of S lanes, R rows per lane), "off" (allowed, not taken) or "none"."""
+        import re
+        return re.findall(r" tile=(\w+)", self.describe())
 
     def waves_per_solve(self):
         """Waves per solve (team size) of each bucket, in describe() order."""

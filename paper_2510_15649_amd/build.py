@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libladlasso.so")
 
-SOURCES = ["ladl_solve_wave.hip", "ladl_solve_plain.hip", "ladl_cv.hip", "ladl_brute.hip", "ladl_noalloc.hip",
+SOURCES = ["ladl_solve_wave.hip", "ladl_solve_tile.hip", "ladl_solve_plain.hip", "ladl_cv.hip", "ladl_brute.hip", "ladl_noalloc.hip",
            "ladl_api.cpp"]
 
 FLAGS = [

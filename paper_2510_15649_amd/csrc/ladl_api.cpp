@@ -67,6 +67,12 @@ struct Bucket {
     int nlds = 0;              // with the workspace: columns of X kept in LDS
     int per_cu = 0;
     int64_t ws_off = 0;        // this bucket's slice of the workspace
+    int nmax = 0;              // largest n in the bucket
+    // tile schedule (n <= 64): the tile kernel's coordinate descent first,
+    // in segments of tile_s lanes with tile_rs rows per lane, then the wave
+    // kernel from its points
+    bool tile_ok = false, tile = false;
+    int tile_s = 0, tile_rs = 0, tile_grid = 0;
 };
 
 struct ladl_plan_s {
@@ -86,6 +92,7 @@ struct ladl_plan_s {
     float *d_wws = nullptr;      // wave kernel workspace (buckets with X outside LDS)
     int64_t wws_floats = 0;
     float *d_bw = nullptr;       // backward: 32 floats per solve (plans with each problem once)
+    float *d_seed = nullptr;     // tile stage output, laid out like b (b_len floats)
     int32_t *d_bf_order = nullptr; // vertex enumeration: solves grouped by p (built on first use)
     std::vector<std::pair<int, int>> bf_buckets; // (p, count) in d_bf_order order
     // buckets run concurrently on streams forked from the caller's stream
@@ -108,6 +115,11 @@ struct ladl_graph_s {
 
 static int layout_workspace(ladl_plan_t pl);
 static void set_schedule(ladl_plan_t pl, Bucket &b, bool xg, bool dense = false, int tw = 1);
+static void set_tile(ladl_plan_t pl, Bucket &b, bool on);
+static int alloc_seed(ladl_plan_t pl);
+// queue counters: the wave kernel's of bucket i at i, the tile kernel's at
+// buckets + i
+static int num_counters(ladl_plan_t pl) { return 2 * (int)pl->buckets.size(); }
 
 // exported functions: C linkage comes from their declarations in ladlasso.h
 
@@ -139,6 +151,7 @@ void ladl_default_options(ladl_options *o)
     o->schedule = -1;
     o->chop_range = 0.03125f;
     o->team = 0;
+    o->tile = 0;
 }
 
 int ladl_create(ladl_handle_t *handle)
@@ -188,6 +201,9 @@ static int check_options(const ladl_options *o)
         return fail(LADL_EINVAL, "chop_range must be finite and > 0");
     if (o->team != 0 && o->team != 1 && o->team != 2 && o->team != 4)
         return fail(LADL_EINVAL, "team must be 0, 1, 2 or 4 (got %d)", o->team);
+    if (o->tile < 0 || o->tile > 2) return fail(LADL_EINVAL, "tile must be 0, 1 or 2 (got %d)", o->tile);
+    if (o->tile == 2 && (o->flags & LADL_FLAG_QUADRATURE))
+        return fail(LADL_EINVAL, "the tile schedule runs the weighted-median update; it excludes LADL_FLAG_QUADRATURE");
     return LADL_OK;
 }
 
@@ -216,6 +232,7 @@ static void plan_free_device(ladl_plan_s *pl)
     (void)hipFree(pl->d_gws);
     (void)hipFree(pl->d_wws);
     (void)hipFree(pl->d_bw);
+    (void)hipFree(pl->d_seed);
     (void)hipFree(pl->d_bf_order);
     for (hipStream_t st : pl->bstreams) (void)hipStreamDestroy(st);
     for (hipEvent_t ev : pl->ev_join) (void)hipEventDestroy(ev);
@@ -342,7 +359,11 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         }
         if (ids.empty()) continue;
         std::stable_sort(ids.begin(), ids.end(), cost_gt);
-        for (int s : ids) b.pmax = std::max(b.pmax, (int)pl->p[pl->problem[s]]);
+        for (int s : ids) {
+            const int k = pl->problem[s];
+            b.pmax = std::max(b.pmax, (int)pl->p[k]);
+            b.nmax = std::max(b.nmax, (int)(pl->row_off[k + 1] - pl->row_off[k]));
+        }
         b.count = (int)ids.size();
         order.insert(order.end(), ids.begin(), ids.end());
         const bool xg = o.schedule >= 0 || R >= 32 || wave_lds_bytes(R, b.pmax, false, 0, 1) > LDS_RESIDENT_MAX;
@@ -361,6 +382,11 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         if (b.tw == 1 && wave_has_dense(R) &&
             (o.schedule == 1 || (o.schedule == -1 && b.count > DENSE_MIN_ROUNDS * b.grid)))
             set_schedule(pl, b, true, true);
+        {
+            int ts, trs;
+            b.tile_ok = R == 1 && !(o.flags & LADL_FLAG_QUADRATURE) && tile_shape_for(b.nmax, ts, trs);
+        }
+        set_tile(pl, b, b.tile_ok && o.tile == 2);
         pl->buckets.push_back(b);
     }
     // plain kernel: all solves, decreasing cost
@@ -371,7 +397,7 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         return (pl->row_off[ka + 1] - pl->row_off[ka]) * pl->p[ka] > (pl->row_off[kc + 1] - pl->row_off[kc]) * pl->p[kc];
     });
     hipError_t e;
-    std::vector<int32_t> zeros(pl->buckets.size() + 1, 0);
+    std::vector<int32_t> zeros(2 * pl->buckets.size() + 1, 0);
     if ((e = upload(&pl->d_row_off, pl->row_off)) != hipSuccess || (e = upload(&pl->d_x_off, pl->x_off)) != hipSuccess ||
         (e = upload(&pl->d_b_off, pl->b_off)) != hipSuccess || (e = upload(&pl->d_p, pl->p)) != hipSuccess ||
         (e = upload(&pl->d_problem, pl->problem)) != hipSuccess || (e = upload(&pl->d_order, order)) != hipSuccess ||
@@ -382,7 +408,7 @@ int ladl_plan_create(ladl_handle_t h, const ladl_layout *lay, const ladl_options
         delete pl;
         return hipfail(e, "plan upload");
     }
-    if ((rc = layout_workspace(pl)) != LADL_OK) {
+    if ((rc = layout_workspace(pl)) != LADL_OK || (rc = alloc_seed(pl)) != LADL_OK) {
         plan_free_device(pl);
         delete pl;
         return rc;
@@ -518,6 +544,28 @@ static void set_schedule(ladl_plan_t pl, Bucket &b, bool xg, bool dense, int tw)
     b.grid = (int)std::min<int64_t>(b.count, (int64_t)b.per_cu * pl->h->num_cu);
 }
 
+static void set_tile(ladl_plan_t pl, Bucket &b, bool on)
+{
+    b.tile = on && b.tile_ok && tile_shape_for(b.nmax, b.tile_s, b.tile_rs);
+    if (!b.tile) return;
+    const int per_cu = std::max(1, tile_max_blocks_per_cu(b.tile_s, b.tile_rs, b.pmax));
+    const int per_block = tile_solves_per_block(b.tile_s);
+    b.tile_grid = (int)std::min<int64_t>((b.count + per_block - 1) / per_block, (int64_t)per_cu * pl->h->num_cu);
+}
+
+// the tile stage's output buffer, once any bucket takes the tile schedule
+static int alloc_seed(ladl_plan_t pl)
+{
+    const bool any = std::any_of(pl->buckets.begin(), pl->buckets.end(), [](const Bucket &b) { return b.tile; });
+    if (!any || pl->d_seed) return LADL_OK;
+    hipError_t e = hipMalloc((void **)&pl->d_seed, sizeof(float) * (size_t)std::max<int64_t>(pl->b_len, 1));
+    if (e != hipSuccess) {
+        pl->d_seed = nullptr;
+        return hipfail(e, "tile stage buffer");
+    }
+    return LADL_OK;
+}
+
 static hipError_t launch_bucket(ladl_plan_t pl, size_t bi, const SolveArgs &base, hipStream_t s)
 {
     const Bucket &bk = pl->buckets[bi];
@@ -527,6 +575,18 @@ static hipError_t launch_bucket(ladl_plan_t pl, size_t bi, const SolveArgs &base
     a.counter = pl->d_counters + bi;
     a.pmax = bk.pmax;
     a.nlds = bk.nlds;
+    if (bk.tile && a.t0 == 0) {
+        // the cold start's descent and chop on tiles, then the wave kernel
+        // from their points
+        if (!pl->d_seed) return hipErrorInvalidValue;
+        SolveArgs at = a;
+        at.t1 = 1;
+        at.b_out = pl->d_seed;
+        at.counter = pl->d_counters + pl->buckets.size() + bi;
+        hipError_t e = launch_tile(bk.tile_s, bk.tile_rs, at, bk.tile_grid, s);
+        if (e != hipSuccess) return e;
+        a.b_seed = pl->d_seed;
+    }
     if (bk.xg) {
         a.gws = pl->d_wws + bk.ws_off;
         a.gws_stride = (int64_t)wave_ws_floats_host(bk.R / bk.tw, bk.pmax, bk.nlds, bk.tw);
@@ -539,7 +599,7 @@ static int enqueue_wave(ladl_plan_t pl, const float *X, const float *y, const fl
                         int t1, hipStream_t s, bool capturing = false)
 {
     const bool timed = pl->profiling && !capturing;
-    hipError_t e = launch_reset(pl->d_counters, (int)pl->buckets.size(), s);
+    hipError_t e = launch_reset(pl->d_counters, num_counters(pl), s);
     if (e != hipSuccess) return hipfail(e, "queue reset launch");
     const bool fork = pl->buckets.size() > 1;
     if (fork && (e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return hipfail(e, "fork event");
@@ -698,8 +758,9 @@ int ladl_graph_destroy(ladl_graph_t g)
     return LADL_OK;
 }
 
-// Tuning cache: one line per decision, "<device name> <R> <pmax> <xg>", in
-// the file named by LADL_TUNE_CACHE (optional).
+// Tuning cache: one line per decision, "<device name> <R> <pmax> <choice>"
+// (the autotuner's candidate number), in the file named by LADL_TUNE_CACHE
+// (optional).
 static std::string device_name(int dev)
 {
     hipDeviceProp_t prop;
@@ -750,12 +811,17 @@ int ladl_autotune(ladl_plan_t pl, const float *X, const float *y, const float *l
     }
     // candidates per bucket: 0 = X in LDS, 1 = X in the HBM workspace,
     // 2 = the HBM workspace with the dense kernel variant, 3 and 4 = the HBM
-    // workspace with a team of 2 or 4 waves per solve
-    auto apply = [&](Bucket &bk, int v) { set_schedule(pl, bk, v != 0, v == 2, v == 3 ? 2 : (v == 4 ? 4 : 1)); };
+    // workspace with a team of 2 or 4 waves per solve; for n <= 64 each of
+    // these also with the tile stage in front (value + 8)
+    auto apply = [&](Bucket &bk, int v) {
+        const int w = v & 7;
+        set_schedule(pl, bk, w != 0, w == 2, w == 3 ? 2 : (w == 4 ? 4 : 1));
+        set_tile(pl, bk, (v & 8) != 0);
+    };
     for (size_t bi = 0; bi < pl->buckets.size() && rc == LADL_OK; ++bi) {
         Bucket &bk = pl->buckets[bi];
         const int forced = pl->opt.team; // 0: the team size is tuned too
-        bool can[5];
+        bool can[13] = {};
         can[0] = bk.R < 32 && wave_lds_bytes(bk.R, bk.pmax, false, 0, 1) <= pl->h->lds_max;
         can[1] = true;
         can[2] = wave_has_dense(bk.R);
@@ -765,24 +831,29 @@ int ladl_autotune(ladl_plan_t pl, const float *X, const float *y, const float *l
             const int tw = v == 3 ? 2 : (v == 4 ? 4 : 1);
             if (forced > 0 && tw != forced) can[v] = false;
         }
+        // tiles: where the bucket allows them, unless the option fixes them
+        for (int v = 0; v < 5; ++v) {
+            can[v + 8] = can[v] && bk.tile_ok && pl->opt.tile != 1;
+            if (pl->opt.tile == 2 && bk.tile_ok) can[v] = false;
+        }
         int ncand = 0;
-        for (int v = 0; v < 5; ++v) ncand += can[v] ? 1 : 0;
+        for (int v = 0; v < 13; ++v) ncand += can[v] ? 1 : 0;
         if (ncand < 2) continue; // nothing to choose
         int cached = cache_lookup(dev, bk.R, bk.pmax);
-        if (cached >= 0 && cached <= 4 && can[cached]) {
+        if (cached >= 0 && cached <= 12 && can[cached]) {
             apply(bk, cached);
             continue;
         }
         float best_ms = 1e30f;
-        int best_v = bk.tw == 4 ? 4 : (bk.tw == 2 ? 3 : (bk.dense ? 2 : (bk.xg ? 1 : 0)));
-        for (int v = 0; v < 5 && rc == LADL_OK; ++v) {
+        int best_v = (bk.tw == 4 ? 4 : (bk.tw == 2 ? 3 : (bk.dense ? 2 : (bk.xg ? 1 : 0)))) + (bk.tile ? 8 : 0);
+        for (int v = 0; v < 13 && rc == LADL_OK; ++v) {
             if (!can[v]) continue;
             apply(bk, v);
-            if ((rc = layout_workspace(pl)) != LADL_OK) break;
+            if ((rc = layout_workspace(pl)) != LADL_OK || (rc = alloc_seed(pl)) != LADL_OK) break;
             SolveArgs a = base_args(pl, X, y, lam, nullptr, b, obj, active, zr, st, nullptr, 0, pl->L);
             float ms = 0.f;
             for (int rep = 0; rep < 2; ++rep) { // first run warms up
-                if ((e = launch_reset(pl->d_counters, (int)pl->buckets.size(), s)) != hipSuccess ||
+                if ((e = launch_reset(pl->d_counters, num_counters(pl), s)) != hipSuccess ||
                     (e = hipEventRecord(e0, s)) != hipSuccess || (e = launch_bucket(pl, bi, a, s)) != hipSuccess ||
                     (e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
                     (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
@@ -801,6 +872,7 @@ int ladl_autotune(ladl_plan_t pl, const float *X, const float *y, const float *l
         }
     }
     if (rc == LADL_OK) rc = layout_workspace(pl);
+    if (rc == LADL_OK) rc = alloc_seed(pl);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
@@ -853,10 +925,15 @@ int ladl_plan_describe(ladl_plan_t pl, char *buf, int64_t len)
             snprintf(place, sizeof place, "HBM workspace, %d columns in LDS%s", b.nlds, b.dense ? " (dense)" : "");
         else
             snprintf(place, sizeof place, "LDS");
+        char tile[64];
+        if (b.tile)
+            snprintf(tile, sizeof tile, "tile=%dx%d grid=%d", b.tile_s, b.tile_rs, b.tile_grid);
+        else
+            snprintf(tile, sizeof tile, "tile=%s", b.tile_ok ? "off" : "none");
         snprintf(line, sizeof line,
-                 "bucket R=%d (n<=%d) pmax=%d solves=%d grid=%d (%d/CU) waves/solve=%d X in %s lds=%zuB\n", b.R,
-                 64 * b.R, b.pmax, b.count, b.grid, b.per_cu, b.tw, place,
-                 wave_lds_bytes(b.R / b.tw, b.pmax, b.xg, b.nlds, b.tw));
+                 "bucket R=%d (n<=%d) pmax=%d solves=%d grid=%d (%d/CU) waves/solve=%d X in %s lds=%zuB %s\n",
+                 b.R, 64 * b.R, b.pmax, b.count, b.grid, b.per_cu, b.tw, place,
+                 wave_lds_bytes(b.R / b.tw, b.pmax, b.xg, b.nlds, b.tw), tile);
         s += line;
     }
     std::strncpy(buf, s.c_str(), (size_t)len - 1);

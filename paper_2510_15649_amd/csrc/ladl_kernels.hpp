@@ -33,6 +33,8 @@ struct SolveArgs {
     DevOpt opt;
     int32_t pmax;         // largest p in the bucket (LDS carve-up)
     int32_t nlds;         // with the workspace: columns of X kept in LDS
+    const float *b_seed;  // wave kernel, n <= 64: start of path step 0
+                          // (laid out like b_out), or null
 };
 
 struct BackwardArgs {
@@ -89,6 +91,15 @@ int wave_max_blocks_per_cu(int Rt, int pmax, bool xg, bool dense, int tw, bool q
 hipError_t launch_reset(int32_t *counters, int n, hipStream_t s);
 hipError_t launch_wave(int Rt, bool xg, bool dense, int tw, bool quad, const SolveArgs &a, int grid, hipStream_t s);
 hipError_t launch_plain(const SolveArgs &a, int NM, int64_t nthreads, hipStream_t s);
+// tile kernel (n <= 64): segments of S lanes with RS row slots per lane, one
+// solve per segment, 64 / S solves per one-wave workgroup.  Writes the end
+// point of the descent and chop of path steps t0 .. t1 to a.b_out (the host
+// runs it on step 0: the wave kernel's seed).
+bool tile_shape_for(int nmax, int &S, int &RS);
+size_t tile_lds_bytes(int S, int RS, int pmax);
+int tile_solves_per_block(int S);
+int tile_max_blocks_per_cu(int S, int RS, int pmax);
+hipError_t launch_tile(int S, int RS, const SolveArgs &a, int grid, hipStream_t s);
 int64_t plain_scratch_floats(int NM, int64_t nthreads);
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t launch_cv_gather(const CvArgs &a, hipStream_t s);

@@ -1412,6 +1412,15 @@ LADL_INL void solve_item(Wave<R, XG, TW> &w, const SolveArgs &a, int s)
         const int64_t o = (int64_t)s * a.path_len + t;
         float *bout = a.b_out + bbase + (int64_t)t * p;
         const float lam_in = a.lam[o];
+        // the cold start seeded by the tile stage, which ran the chop already
+        bool seeded = false;
+        if constexpr (R == 1) {
+            if (a.b_seed && t == 0) {
+                const float b1 = (l < p) ? a.b_seed[bbase + l] : 0.f;
+                bv = (l < p && __builtin_isfinite(b1)) ? b1 : 0.f;
+                seeded = true;
+            }
+        }
         w.c_sweeps = w.c_updates = w.c_probes = w.c_pivots = 0;
         int status;
         float fout = 0.f;
@@ -1430,7 +1439,7 @@ LADL_INL void solve_item(Wave<R, XG, TW> &w, const SolveArgs &a, int s)
             int vs = -1;
             float u = 0.f, c = 0.f, fv = 0.f;
             const bool snap = !(w.opt.flags & FLAG_NO_SNAP);
-            const int rounds = (p < 2) ? 0 : ((w.opt.max_rounds < 0) ? p : w.opt.max_rounds);
+            const int rounds = (p < 2 || seeded) ? 0 : ((w.opt.max_rounds < 0) ? p : w.opt.max_rounds);
             const float B = (w.lam > 0.f) ? w.ynorm1 / w.lam : FINF;
             static_assert(sizeof(Chop) <= 4 * CHOP_FLOATS, "chop state does not fit its LDS slot");
             Chop &q = *w.chop;

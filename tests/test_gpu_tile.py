@@ -1,0 +1,273 @@
+"""GPU: the tile schedule (options.tile), which runs the cold start of
+problems with n <= 64 several to a wavefront (segments of 16 or 32 lanes):
+coordinate descent, the chop along the locus of axis-wise minima, descent;
+the wavefront kernel starts from that point, snaps and certifies it (and
+finishes it where needed) without a chop of its own.
+
+Checked here, always through the C ABI:
+- parity with the oracle for each tile shape (16 lanes x 1 row, 16 x 2,
+  32 x 2) over ragged n and p = 1 .. 32, and on the paper's problem sizes;
+- the tile stage's points are axis-wise minima: with the snap and the chop
+  off, the wavefront stage started from them finds nothing to change in
+  its first sweep, and an fp64 search of every coordinate's section on the
+  host finds no lower value;
+- a lambda path of small problems gives the same bits as a HIP graph of
+  per-step launches as in one launch, and matches the oracle's path;
+- the tile stage's chop on its own (the wavefront stage runs no probe for
+  a seeded step) reaches the p = 2 minima with the finisher off, and with
+  the snap off too, and escapes the stuck instance (Sections 3.5-3.6);
+- degenerate inputs, status codes, option validation, and the autotuner's
+  choice between tiles and one wavefront per problem."""
+import numpy as np
+import pytest
+
+import paper_2510_15649_amd as L
+from paper_2510_15649_amd import workloads as W
+from parity import compare, oracle_ref, to_numpy
+from test_gpu_chop import exact_min, p2_workload
+from test_gpu_parity import _pack, assert_parity, gpu_solve
+
+pytestmark = pytest.mark.gpu
+OK = (L.CERTIFIED, L.NONUNIQUE)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def small_blocks(ns, ps, seed):
+    rng = np.random.default_rng(seed)
+    blocks, lams = [], []
+    for n in ns:
+        for p in ps:
+            X = rng.standard_normal((n, p))
+            q = min(p, 3)
+            y = X[:, :q] @ rng.uniform(-3, 3, q) + rng.laplace(0, 1, n)
+            blocks.append((X, y))
+            lams.append(float(10 ** rng.uniform(-2, 1)))
+    return blocks, lams
+
+
+SHAPES = {
+    "16x1": [1, 2, 3, 7, 15, 16],
+    "16x2": [1, 5, 16, 17, 24, 31, 32],
+    "32x2": [2, 17, 32, 33, 40, 47, 63, 64],
+}
+
+
+def tile_of(plan):
+    """The tile schedule of the plan's n <= 64 bucket."""
+    for (R, nmax, pmax, count), t in zip(plan.buckets(), plan.tiles()):
+        if R == 1:
+            return t
+    return None
+
+
+@pytest.mark.parametrize("shape", list(SHAPES))
+def test_tile_parity_shapes(torch, shape):
+    blocks, lams = small_blocks(SHAPES[shape], [1, 2, 3, 5, 8, 17, 32], seed=41 + len(shape))
+    w = _pack(blocks, lams)
+    plan, g = gpu_solve(torch, w, tile=2)
+    print(plan.describe(), flush=True)
+    assert tile_of(plan) == shape
+    assert_parity(w, g, oracle_ref(w), min_strict=0.5)
+
+
+def test_tile_paper_sizes(torch):
+    """The paper's sizes (n 10..30, p 1..5, three lambdas): every output
+    against the oracle, and the same objectives as one wavefront per
+    problem."""
+    w = W.paper_sizes(num_problems=512)
+    plan, g = gpu_solve(torch, w, tile=2)
+    print(plan.describe(), flush=True)
+    assert tile_of(plan) == "16x2"
+    fails, st = compare(w, g, oracle_ref(w))
+    print(st, flush=True)
+    assert not fails, fails[:5]
+    assert st["strict"] >= 0.95 * st["unique"], st
+    _, gw = gpu_solve(torch, w, tile=1)
+    rel = np.abs(g["obj"].astype(np.float64) - gw["obj"]) / np.maximum(gw["obj"], 1e-30)
+    assert np.max(rel) <= 2e-5, np.max(rel)
+
+
+def section_gap(Xk, yk, lam, b):
+    """max over coordinates j of f(b) - min_t f(b with b_j = t), in fp64,
+    the section minimum taken over all its kinks; and f(b)."""
+    b = b.astype(np.float64)
+    r = yk - Xk @ b
+    f = np.abs(r).sum() + lam * np.abs(b).sum()
+    gap = 0.0
+    for j in range(Xk.shape[1]):
+        x = Xk[:, j]
+        nz = x != 0
+        kinks = np.concatenate([b[j] + r[nz] / x[nz], [0.0]])
+        # r_i(t) = r_i - x_ij (t - b_j) at every kink t
+        R = r[:, None] - x[:, None] * (kinks[None, :] - b[j])
+        g = np.abs(R).sum(axis=0) + lam * (np.abs(b).sum() - abs(b[j]) + np.abs(kinks))
+        gap = max(gap, f - float(g.min()))
+    return gap, f
+
+
+def test_tile_points_are_axiswise_minima(torch):
+    """Snap and chop off, and a sweep cap high enough for both stages to
+    converge: the wavefront stage only runs coordinate descent from the tile
+    stage's point, so its sweeps show how far from an axis-wise minimum that
+    point was.  It mostly needs the one confirming sweep (a few more where
+    residuals recomputed from scratch round a zero residual off zero), far
+    fewer in total than from b = 0, and every final point is an axis-wise
+    minimum by an fp64 search of each coordinate's section on the host."""
+    blocks, lams = small_blocks([4, 12, 16, 20, 30, 32, 40, 55, 64], [1, 2, 4, 8, 16, 32], seed=77)
+    w = _pack(blocks, lams)
+    opts = dict(flags=L.FLAG_NO_SNAP | L.FLAG_GOLDEN, max_rounds=0, max_sweeps=500)
+    plan, g = gpu_solve(torch, w, tile=2, **opts)
+    assert tile_of(plan) == "32x2"
+    sw = g["iters"].reshape(-1, 4)[:, 0]
+    _, g1 = gpu_solve(torch, w, tile=1, **opts)
+    sw1 = g1["iters"].reshape(-1, 4)[:, 0]
+    print(f"wave-stage sweeps from the tile point: {sw.sum()} ({np.bincount(sw).tolist()}); "
+          f"from b = 0: {sw1.sum()}", flush=True)
+    assert np.median(sw) == 1 and (sw == 1).mean() >= 0.75, np.bincount(sw)
+    assert sw.sum() <= 0.35 * sw1.sum(), (sw.sum(), sw1.sum())
+    assert np.all(g["status"] == L.MAXITER)
+    ps = w.p[w.problem]
+    off = np.concatenate([[0], np.cumsum(ps)[:-1]])
+    for s in range(w.num_solves):
+        Xk, yk = w.block(s)
+        gap, f = section_gap(Xk, yk, float(w.lam[s]), g["b"][off[s]:off[s] + ps[s]])
+        assert gap <= 1e-5 * max(f, 1e-30), (s, gap, f)
+
+
+def small_path_workload(count=24, path_len=4):
+    """Problems of the large ragged recipe with n <= 64, on a lambda path."""
+    ks = [k for k in range(4000) if int(W._rng(W.BASE_SEED + 4000, k).integers(32, 2049)) <= 64][:count]
+    return W.config4(problems=ks, path_len=path_len)
+
+
+def test_tile_path_graph_matches_one_launch(torch):
+    w = small_path_workload()
+    print(f"[gpu] tile path {w.name}", flush=True)
+    d = L.to_device(w)
+    plan = L.Plan.for_workload(w, tile=2)
+    assert tile_of(plan) == "32x2"
+    ref_out = plan.solve(d["X"], d["y"], d["lam"])
+    torch.cuda.synchronize()
+    ref = to_numpy(ref_out)
+    out = plan.alloc_outputs()
+    graph = plan.graph(d["X"], d["y"], d["lam"], out)
+    for rep in range(3):
+        graph.launch()
+        torch.cuda.synchronize()
+        got = to_numpy(out)
+        for key in ("b", "obj", "active", "zero_rows", "status"):
+            assert np.array_equal(got[key], ref[key]), (rep, key)
+    fails, st = compare(w, ref, oracle_ref(w))
+    print(st, flush=True)
+    assert not fails, fails[:5]
+
+
+@pytest.mark.parametrize("split", [0, L.FLAG_GOLDEN], ids=["thirds", "golden"])
+@pytest.mark.parametrize("snap", [True, False], ids=["snap", "nosnap"])
+def test_tile_chop_without_finisher(torch, split, snap):
+    """p = 2, n 3 .. 63 (all on tiles): the chop of the tile stage alone
+    reaches the minimum; the wavefront stage adds no probe and no pivot
+    (without the snap it only confirms the descent)."""
+    w = p2_workload(num=128, seed=33)
+    keep = [s for s in range(w.num_solves) if w.n(s) <= 64]
+    w = W._pack("p=2, n <= 64", [w.block(s) for s in keep], [2] * len(keep), np.arange(len(keep)),
+                [float(w.lam[s]) for s in keep], 1)
+    fstar = exact_min(w)
+    flags = L.FLAG_NO_FINISHER | split | (0 if snap else L.FLAG_NO_SNAP)
+    plan, g = gpu_solve(torch, w, tile=2, flags=flags, max_rounds=1)
+    assert tile_of(plan) == "32x2"
+    it = g["iters"].reshape(-1, 4)
+    assert np.all(it[:, 2] == 0) and np.all(it[:, 3] == 0)
+    rel = np.abs(g["obj"].astype(np.float64) - fstar) / np.maximum(fstar, 1e-30)
+    assert np.max(rel) <= 1e-5, (np.argmax(rel), np.max(rel))
+    if snap:
+        assert np.isin(g["status"], OK).mean() >= 0.97, np.bincount(g["status"], minlength=6)
+    else:
+        assert np.all(g["status"] == L.MAXITER)
+    # without the chop (max_rounds = 0) the descent stalls on many of them
+    _, g0 = gpu_solve(torch, w, tile=2, flags=flags, max_rounds=0)
+    rel0 = (g0["obj"].astype(np.float64) - fstar) / np.maximum(fstar, 1e-30)
+    assert (rel0 > 1e-5).sum() >= 16, (rel0 > 1e-5).sum()
+
+
+def test_tile_stuck_instance(torch):
+    """The golden stuck instance (n = 6, p = 2): the tile stage's descent
+    stops 0.55 above the optimum; its chop reaches the optimum."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "stuck2d.json")))
+    X, y = np.array(g["X"]), np.array(g["y"])
+    w = W._pack("stuck2d", [(X, y)], [2], [0], [g["lambda"]], 1)
+    flags = L.FLAG_NO_FINISHER | L.FLAG_NO_SNAP | L.FLAG_GOLDEN
+    out = {r: gpu_solve(torch, w, tile=2, flags=flags, max_rounds=r)[1] for r in (0, 1)}
+    assert out[0]["obj"][0] >= g["f_opt"] + 0.5
+    assert abs(out[1]["obj"][0] - g["f_opt"]) <= 1e-5 * g["f_opt"]
+    np.testing.assert_allclose(out[1]["b"], g["b_opt"], rtol=1e-4, atol=1e-4)
+
+
+def test_tile_degenerate_inputs_and_status(torch):
+    rng = np.random.default_rng(8)
+    n, p = 40, 6
+    X = rng.standard_normal((n, p))
+    y = X @ np.array([1.0, 0, -2, 0, 0, 0.5]) + rng.laplace(0, 1, n)
+    Xz = X.copy()
+    Xz[:, 3] = 0.0
+    Xd = np.repeat(X[:20], 2, axis=0)
+    yd = np.repeat(y[:20], 2)
+    Xn = X.copy()
+    Xn[5, 2] = np.nan
+    yi = y.copy()
+    yi[3] = np.inf
+    blocks = [(X, np.zeros(n)), (Xz, y), (Xd, yd), (X, y), (X, y), (Xn, y), (X, yi), (X, y), (X[:1, :1], y[:1])]
+    lmax = float(np.max(np.abs(X.astype(np.float32).astype(np.float64).T @ np.sign(y))))
+    w = _pack(blocks, [1.0, 1.0, 0.5, 1.5 * lmax, 0.0, 1.0, 1.0, -1.0, 0.3])
+    plan, g = gpu_solve(torch, w, tile=2)
+    assert tile_of(plan) == "32x2"
+    assert list(g["status"][5:8]) == [L.NONFINITE, L.NONFINITE, L.BADLAMBDA]
+    good = [0, 1, 2, 3, 4, 8]
+    fails, st = compare(w, g, oracle_ref(w, solves=good), solves=good)
+    assert not fails, fails
+    assert g["obj"][0] == 0.0 and np.all(g["b"][:p] == 0)
+    assert g["b"][p * 1 + 3] == 0.0
+    assert np.all(g["b"][3 * p: 4 * p] == 0) and g["active"][3] == 0
+
+
+def test_tile_options(torch):
+    ro = np.array([0, 10, 20], dtype=np.int64)
+    with pytest.raises(L.LadlError) as e:
+        L.Plan(ro, 3, x_len=60, y_len=20, tile=3)
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LadlError) as e:
+        L.Plan(ro, 3, x_len=60, y_len=20, tile=2, flags=L.FLAG_QUADRATURE)
+    assert e.value.code == L.EINVAL
+    assert tile_of(L.Plan(ro, 3, x_len=60, y_len=20)) == "off"
+    assert tile_of(L.Plan(ro, 3, x_len=60, y_len=20, flags=L.FLAG_QUADRATURE)) == "none"
+    big = np.array([0, 100, 200], dtype=np.int64)
+    assert L.Plan(big, 3, x_len=600, y_len=200, tile=2).tiles() == ["none"]
+
+
+def test_tile_autotune(torch, tmp_path, monkeypatch):
+    """The autotuner times each schedule of the n <= 64 bucket with and
+    without the tile stage, keeps the faster, and the tuned plan keeps
+    parity; a second plan reads the choice from the cache."""
+    monkeypatch.setenv("LADL_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    w = W.paper_sizes(num_problems=2048)
+    plan = L.Plan.for_workload(w)
+    d = L.to_device(w)
+    plan.autotune(d["X"], d["y"], d["lam"], plan.alloc_outputs())
+    print(plan.describe(), flush=True)
+    assert tile_of(plan) in ("16x2", "off")
+    out = to_numpy(plan.solve(d["X"], d["y"], d["lam"]))
+    torch.cuda.synchronize()
+    sample = np.sort(np.random.default_rng(5).choice(w.num_solves, size=256, replace=False))
+    fails, st = compare(w, out, oracle_ref(w, solves=sample), solves=sample)
+    assert not fails, fails[:5]
+    plan2 = L.Plan.for_workload(w)
+    plan2.autotune(d["X"], d["y"], d["lam"], plan2.alloc_outputs())
+    assert plan2.describe() == plan.describe()
