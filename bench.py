@@ -52,7 +52,7 @@ def make_workload(cfg: str, **kw):
     from paper_2510_15649_amd import workloads as W
     return {"c1": lambda: W.config1(**kw), "c1path": lambda: W.config1(as_path=True), "c2": lambda: W.config2(),
             "c3": lambda: W.config3(), "c4": lambda: W.config4(),
-            "c4s": lambda: W.config4(problems=range(4096))}[cfg]()
+            "c4s": lambda: W.config4(problems=range(4096)), "paper": lambda: W.paper_sizes(**kw)}[cfg]()
 
 
 def kernel_source_sha():
@@ -455,6 +455,8 @@ def main():
                     help="the quadrature variant: 1-D sections minimised by a quadrature search of their values")
     ap.add_argument("--team", type=int, default=0,
                     help="waves per solve for n > 1024 (0: the library's choice; 1, 2 or 4)")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="tile schedule for n <= 64 (0: the library's choice; 1 off; 2 on)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
@@ -494,9 +496,10 @@ def main():
         rng = np.random.default_rng(2024)
         psolves = np.sort(rng.choice(w.num_solves, size=min(args.parity_sample, w.num_solves), replace=False))
     m = measure(L, torch, w, args.steps, args.warmup, psolves, args.autotune, max_rounds=args.max_rounds,
-                flags=flags, team=args.team)
+                flags=flags, team=args.team, tile=args.tile)
     ms = m["ms"]
-    default_run = args.max_rounds == 1 and flags == default_flags and not args.autotune and args.team == 0
+    default_run = (args.max_rounds == 1 and flags == default_flags and not args.autotune and args.team == 0 and
+                   args.tile == 0)
     summary = {"c4": "k_wave_c4_full_hbm_bytes.md", "c2": "k_wave_c2_kernel_stats.md",
                "c1": "k_wave_c1_hbm_bytes.md"}.get(args.config) if default_run else None
     roof = alu_roofline(m, summary)
@@ -566,7 +569,7 @@ def main():
         "dtype": "f32", "data": "synthetic (seeded generator, no dataset)",
         "config": {"workload": w.name, "solves_per_step": m["n_out"], "max_rounds": args.max_rounds,
                    "golden": bool(flags & L.FLAG_GOLDEN), "quadrature": bool(args.quadrature),
-                   "autotune": bool(args.autotune), "team": args.team,
+                   "autotune": bool(args.autotune), "team": args.team, "tile": args.tile,
                    "parallelism": "1 GPU, one wavefront per solve, buckets side by side",
                    "path_len": w.path_len, "graph_ms_per_step": graph_ms, "graph_equals_in_kernel": graph_same},
         "roofline": roof,
