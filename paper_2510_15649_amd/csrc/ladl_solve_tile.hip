@@ -4,7 +4,7 @@
 // lane i of the segment holding rows i, i + S, ... (RS row slots, n <= S RS).
 // The segment's scalars (b_j, lambda, f, the loop state) are computed
 // identically in all its lanes: every reduction is an xor butterfly (DPP
-// inside a row of 16 lanes, one lane swap across rows), whose two partners
+// inside a row of 16 lanes, one row exchange across rows), whose two partners
 // add the same pair of values, so all lanes of a segment end with the same
 // bits and take the same branches; segments diverge from each other only
 // through the execution mask.
@@ -43,9 +43,21 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// the value of the same lane in the other row of 16 of a 32-lane segment
+// (v_permlane16_swap of gfx950 exchanges the odd rows of its first operand
+// with the even rows of its second: with v in both, an even row finds its
+// partner in the second result, an odd row in the first)
+__device__ __forceinline__ unsigned other_row(unsigned v)
+{
+    const auto sw = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return ((threadIdx.x >> 4) & 1) ? sw[0] : sw[1];
+}
+__device__ __forceinline__ float other_row(float v) { return bitsf((int)other_row((unsigned)fbits(v))); }
+__device__ __forceinline__ int other_row(int v) { return (int)other_row((unsigned)v); }
+
 // xor butterflies over a segment: quad swaps, then the half-row and row
 // mirrors (after the quad steps every quad is uniform, so a mirror pairs
-// whole quads), then for 32-lane segments the swap of its two rows
+// whole quads), then for 32-lane segments the exchange of its two rows
 template <int S>
 __device__ __forceinline__ float seg_sum(float v)
 {
@@ -53,7 +65,7 @@ __device__ __forceinline__ float seg_sum(float v)
     v += dpp<DPP_XOR2>(0.f, v);
     v += dpp<DPP_HMIRROR>(0.f, v);
     v += dpp<DPP_MIRROR>(0.f, v);
-    if constexpr (S == 32) v += __shfl_xor(v, 16);
+    if constexpr (S == 32) v += other_row(v);
     return v;
 }
 
@@ -69,8 +81,8 @@ __device__ __forceinline__ void seg_sum2(float &a, float &b)
     a += dpp<DPP_MIRROR>(0.f, a);
     b += dpp<DPP_MIRROR>(0.f, b);
     if constexpr (S == 32) {
-        a += __shfl_xor(a, 16);
-        b += __shfl_xor(b, 16);
+        a += other_row(a);
+        b += other_row(b);
     }
 }
 
@@ -81,7 +93,7 @@ __device__ __forceinline__ float seg_min(float v)
     v = fminf(v, dpp<DPP_XOR2>(FINF, v));
     v = fminf(v, dpp<DPP_HMIRROR>(FINF, v));
     v = fminf(v, dpp<DPP_MIRROR>(FINF, v));
-    if constexpr (S == 32) v = fminf(v, __shfl_xor(v, 16));
+    if constexpr (S == 32) v = fminf(v, other_row(v));
     return v;
 }
 
@@ -92,7 +104,7 @@ __device__ __forceinline__ int seg_min_i(int v)
     v = min(v, dppi<DPP_XOR2>(INT_MAX, v));
     v = min(v, dppi<DPP_HMIRROR>(INT_MAX, v));
     v = min(v, dppi<DPP_MIRROR>(INT_MAX, v));
-    if constexpr (S == 32) v = min(v, __shfl_xor(v, 16));
+    if constexpr (S == 32) v = min(v, other_row(v));
     return v;
 }
 
