@@ -81,3 +81,48 @@ def test_binding_rejects_bad_tensors():
     with pytest.raises(ValueError, match="required"):
         _check(None, "X", "f32", 8)
     _check(None, "b_init", "f32", 8, optional=True)
+
+
+def header_structs():
+    """Field names, in order, of every `typedef struct { ... } name;`."""
+    src = open(os.path.join(ROOT, "include", "ladlasso.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(\w+)\s*;", src, flags=re.S):
+        fields = [re.findall(r"(\w+)\s*;", decl.strip() + ";")[0] for decl in body.split(";") if decl.strip()]
+        out[name] = fields
+    return out
+
+
+BINDINGS = {"ladl_options": L.Options, "ladl_layout": L.Layout, "ladl_cv_layout": L.CVLayout}
+
+
+def test_binding_structs_match_header(tmp_path):
+    """The ctypes structures of the binding have the header's fields in the
+    header's order, and the same size and offsets as a C compiler gives
+    them: the library writes into them (ladl_default_options), so a
+    mismatch would corrupt memory."""
+    import shutil
+    import subprocess
+    structs = header_structs()
+    assert set(BINDINGS) <= set(structs), structs.keys()
+    for cname, cls in BINDINGS.items():
+        assert [f for f, _ in cls._fields_] == structs[cname], cname
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ladlasso.h"', 'int main(void) {']
+    for cname in BINDINGS:
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in structs[cname]:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, cls in BINDINGS.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
