@@ -168,6 +168,57 @@ def test_tile_path_graph_matches_one_launch(torch):
     assert not fails, fails[:5]
 
 
+def test_tile_path_with_a_hard_first_step(torch):
+    """The same problems on their path reversed (smallest lambda first), so
+    that the seeded cold start needs the chop: the wave stage runs no probe
+    on step 0 (the tile stage chopped), later steps start from the previous
+    certified vertex; every step against the oracle, and the HIP graph
+    equals one launch bit for bit."""
+    w0 = small_path_workload(count=24, path_len=4)
+    S, Lp = w0.num_solves, w0.path_len
+    blocks = [w0.block(k) for k in range(len(w0.p))]
+    lam = w0.lam.reshape(S, Lp)[:, ::-1].ravel()
+    w = W._pack("small c4 problems, ascending lambda path", blocks, w0.p, w0.problem, lam, Lp)
+    d = L.to_device(w)
+    res = {}
+    for tile in (1, 2):
+        plan = L.Plan.for_workload(w, tile=tile)
+        res[tile] = to_numpy(plan.solve(d["X"], d["y"], d["lam"]))
+        torch.cuda.synchronize()
+    it1 = res[1]["iters"].reshape(S, Lp, 4)
+    it2 = res[2]["iters"].reshape(S, Lp, 4)
+    assert (it1[:, 0, 2] > 0).sum() >= 4, it1[:, 0, 2]
+    assert np.all(it2[:, 0, 2] == 0)
+    fails, st = compare(w, res[2], oracle_ref(w))
+    print(st, flush=True)
+    assert not fails, fails[:5]
+    plan = L.Plan.for_workload(w, tile=2)
+    out = plan.alloc_outputs()
+    graph = plan.graph(d["X"], d["y"], d["lam"], out)
+    graph.launch()
+    torch.cuda.synchronize()
+    got = to_numpy(out)
+    for key in ("b", "obj", "active", "zero_rows", "status"):
+        assert np.array_equal(got[key], res[2][key]), key
+
+
+def test_tile_cold_start_from_b_init(torch):
+    """b_init is the tile stage's start: started at the oracle's optimum,
+    the descent and chop keep the optimal value and the wave stage
+    certifies it with no finisher pivot."""
+    blocks, lams = small_blocks([12, 30, 50, 64], [2, 4, 8], seed=91)
+    w = _pack(blocks, lams)
+    ref = oracle_ref(w)
+    d = L.to_device(w)
+    b0 = torch.from_numpy(ref["b"].astype(np.float32)).cuda()
+    plan = L.Plan.for_workload(w, tile=2)
+    g = to_numpy(plan.solve(d["X"], d["y"], d["lam"], b_init=b0))
+    torch.cuda.synchronize()
+    fails, st = compare(w, g, ref)
+    assert not fails, fails[:5]
+    assert np.all(g["iters"].reshape(-1, 4)[:, 3] == 0)
+
+
 @pytest.mark.parametrize("split", [0, L.FLAG_GOLDEN], ids=["thirds", "golden"])
 @pytest.mark.parametrize("snap", [True, False], ids=["snap", "nosnap"])
 def test_tile_chop_without_finisher(torch, split, snap):
