@@ -1,5 +1,6 @@
-// Tile schedule: the paper's cyclic coordinate descent (Sections 3.3-3.4)
-// for small problems (n <= 64), several problems per wavefront.  A wave is
+// Tile schedule: the paper's cyclic coordinate descent and ternary chop
+// (Sections 3.3-3.6) for small problems (n <= 64), several problems per
+// wavefront.  A wave is
 // cut into segments of S = 16 or 32 lanes; each segment runs one solve,
 // lane i of the segment holding rows i, i + S, ... (RS row slots, n <= S RS).
 // The segment's scalars (b_j, lambda, f, the loop state) are computed
@@ -253,7 +254,8 @@ __device__ __forceinline__ float seg_ccd(const Seg<S, RS> &g, float (&r)[RS], in
     return f;
 }
 
-// b := the saved best point (or save it), with its residuals
+// b := the saved best point, or (save) the best point := b; the caller
+// keeps the matching residuals in registers
 template <int S, int RS>
 __device__ __forceinline__ void seg_copy_b(const Seg<S, RS> &g, bool save)
 {
